@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the Dynamic DH-MBIR EM step (arXiv 2305.03284).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may import it; the GPU path never does.  Shares no code with
+the GPU path.
+
+Parity status of each function (what pins it):
+  F / FH, back_project ........ Parseval, inverse, delta, explicit DFT sum,
+                                adjoint identity against the simulator's A
+  normalize ................... mean 0, norm sqrt(p), affine invariance
+  remove_tiptilt .............. plane -> 0, residual orthogonal, idempotent
+  r_init ...................... hand-computed pixel values of Eq. (3)
+  e_step ...................... dense posterior (64x64 inverse) at N=8, a=1
+  qggmrf_rho / qggmrf_weight .. finite differences; majorisation on a grid
+  solve_pixel_r ............... brute-force grid minimiser; no-prior limit r=s
+  r_m_step / phi_m_step ....... pixel-by-pixel sequential ICD at N=8;
+                                surrogate decrease; beta=0 limit phi=theta
+  em / ddh_frame .............. cost_U non-increasing over 200 iterations;
+                                piston invariance; integer-tilt = image shift
+  cost_U ...................... dense Gaussian likelihood at N=8, a=1
+  strehl ...................... S=1 for constant / tilt residual, Marechal
+"""
+from . import ddh, metrics  # noqa: F401
+from .ddh import Params  # noqa: F401
