@@ -1,0 +1,187 @@
+/*
+ * ddh.h -- C ABI of the Dynamic DH-MBIR per-frame EM step on AMD MI355X (gfx950).
+ *
+ * Method: arXiv 2305.03284, "Dynamic DH-MBIR for Phase-Error Estimation from
+ * Streaming Digital-Holography Data".  Model (Forward Model section, Eq. (1)):
+ *   y = A_phi g + w,  A_phi = D_a D(exp(j phi)) F Gamma,  g ~ CN(0, diag r),
+ * F the unitary 2D DFT, Gamma taken as identity.  One frame of the streaming
+ * loop (Dynamic DH-MBIR section, Fig. 1) is
+ *   y <- Normalize(y)                          (Eq. (4))
+ *   phi <- RemoveTipTilt(phi)                  (least-squares plane removal)
+ *   r <- (1-lambda) r + lambda alpha |A_phi^H y|^2    (Eq. (3))
+ *   n_k times: (r, phi) <- EM(r, phi; y)       (DH-MBIR section)
+ * and WriteData(n, r, phi) is ddh_get_phase / ddh_get_reflectance.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are N x N, row-major, C-contiguous.  Complex data is interleaved
+ *     float pairs (re, im) ("complex64").  Device pointers point into HIP
+ *     device memory on the current device; host pointers into host memory.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it unless stated otherwise.
+ *   - Return value: DDH_OK (0) or a negative DDH_E* code; ddh_error_string()
+ *     names it.  Argument checks happen before any device work, so an
+ *     invalid call enqueues nothing and leaves all state unchanged.
+ *   - The library owns every device buffer it allocates (stream state,
+ *     workspace, graphs); the caller owns y and all output buffers.
+ *   - A stream handle is not thread-safe: use it from one host thread at a
+ *     time.  Different handles are independent.
+ */
+#ifndef DDH_H
+#define DDH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define DDH_OK       0
+#define DDH_EINVAL  (-1)   /* null pointer, unsupported N, parameter out of range */
+#define DDH_ENOMEM  (-2)   /* device allocation refused                            */
+#define DDH_EDEVICE (-3)   /* a HIP runtime call failed                            */
+#define DDH_EDATA   (-4)   /* frame rejected: ||y - mean(y)|| = 0 or non-finite    */
+#define DDH_ESTATE  (-5)   /* handle destroyed, or batch/stream mismatch           */
+
+typedef struct ddh_stream_s* ddh_stream_t;
+typedef struct ddh_batch_s* ddh_batch_t;
+
+/* Algorithm parameters (one set per stream).
+ *   N               grid size; one of 64, 128, 256, 512 (paper: N = 256).
+ *   pupil_diameter  circular aperture a (diagonal of D_a) of this diameter in
+ *                   pixels, centred at ((N-1)/2, (N-1)/2): pixel (i, j) is in
+ *                   the pupil iff (2i-N+1)^2 + (2j-N+1)^2 <= diameter^2.
+ *                   0 < diameter <= N*sqrt(2).
+ *   lambda, alpha   weights of Eq. (3), each in [0, 1] (paper: 0.45, 0.025).
+ *   n_k             EM iterations per frame, >= 1 (Fig. 1; paper: 1).
+ *   sigma_w2        noise variance of the normalised data, > 0.
+ *   qg_p, qg_q, qg_T, qg_sigma
+ *                   QGGMRF prior on r: rho(d) = |d|^p/(p s^p) / (1 + |d/(T s)|^(p-q)),
+ *                   1 <= q <= p <= 2, T > 0, s = qg_sigma > 0.
+ *   beta_phi        Gaussian-MRF weight on phi, >= 0:
+ *                   beta * sum over 8-neighbour pupil pairs of b_ij (phi_i - phi_j)^2,
+ *                   b_ij = 1/6 (edge) or 1/12 (diagonal).
+ *   r_floor         positivity floor on r, > 0.
+ */
+typedef struct {
+    int   N;
+    float pupil_diameter;
+    float lambda;
+    float alpha;
+    int   n_k;
+    float sigma_w2;
+    float qg_p;
+    float qg_q;
+    float qg_T;
+    float qg_sigma;
+    float beta_phi;
+    float r_floor;
+} ddh_params;
+
+/* Fill *p with defaults for grid size N: diameter N, lambda 0.45, alpha 0.025,
+ * n_k 1, sigma_w2 0.1, QGGMRF (2, 1.2, 0.1, 0.2), beta_phi 0.5, r_floor 1e-8. */
+int ddh_default_params(int N, ddh_params* p);
+
+/* Create a stream: r <- 0, phi <- 0, n <- 0 (Fig. 1, first line of DDH_MBIR).
+ * Allocates the per-stream device state and workspace (about 44 bytes per
+ * pixel) on the current device and zeroes r and phi on hip_stream.
+ * Errors: DDH_EINVAL (p or out NULL, parameter out of range), DDH_ENOMEM,
+ * DDH_EDEVICE.  On error *out is left unchanged. */
+int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out);
+
+/* Release a stream and its device memory.  Synchronises the device first.
+ * Destroying NULL is DDH_EINVAL.  The handle must not be used afterwards. */
+int ddh_destroy_stream(ddh_stream_t s);
+
+/* One frame of the DDH-MBIR loop (Fig. 1 body): Normalize (Eq. (4)),
+ * RemoveTipTilt, the r initialisation of Eq. (3), then n_k EM iterations.
+ * y: device pointer, N*N complex64, read-only, must stay valid until the
+ * stream reaches this step (no pointer is kept afterwards).  If the frame is
+ * rejected on the device (||y - mean|| zero or non-finite) the state is left
+ * unchanged and the next ddh_status() returns DDH_EDATA.  Increments n. */
+int ddh_step(ddh_stream_t s, const void* y, void* hip_stream);
+
+/* One EM iteration EM(r, phi; y) of the plain DH-MBIR loop (DH-MBIR
+ * section): Normalize y, then E-step, r M-step, phi M-step, with no
+ * RemoveTipTilt and no Eq. (3) initialisation.  Same y contract as ddh_step. */
+int ddh_em(ddh_stream_t s, const void* y, void* hip_stream);
+
+/* WriteData (Fig. 1): copy the current phase phi (radians, unwrapped, zero
+ * off the pupil) or reflectance r (Normalize units) into out, a device
+ * pointer to N*N floats, on hip_stream.  Synchronise before reading. */
+int ddh_get_phase(ddh_stream_t s, float* out, void* hip_stream);
+int ddh_get_reflectance(ddh_stream_t s, float* out, void* hip_stream);
+
+/* Overwrite the state (r, phi, n) from device pointers to N*N floats, for
+ * checkpoint/resume.  r must be >= r_floor; phi should be zero off the pupil. */
+int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n, void* hip_stream);
+
+/* Frames submitted so far (n of Fig. 1). */
+int ddh_frame_count(ddh_stream_t s, long long* n);
+
+/* Synchronise hip_stream and report whether the last frame submitted on s
+ * was rejected (DDH_EDATA) or accepted (DDH_OK). */
+int ddh_status(ddh_stream_t s, void* hip_stream);
+
+/* Grid size and parameters of a stream. */
+int ddh_get_params(ddh_stream_t s, ddh_params* out);
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* FP64 value of the cost that EM does not increase, at the current (r, phi)
+ * for frame y (device pointer, N*N complex64):
+ *   U = sum_i |b_i|^2/(r_i + s2) + log(r_i + s2) + sum_pairs b_ij rho(r_i - r_j)
+ *       + beta sum_pupil_pairs b_ij (phi_i - phi_j)^2,  b = A_phi^H Normalize(y)
+ * (joint MAP cost Eq. (2) of the back-projected model).  Per-pixel terms and
+ * the reduction are FP64.  Synchronises hip_stream; result in *U (host). */
+int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream);
+
+/* FP64 peak Strehl ratio (Algorithm Parameters and Metrics section)
+ *   S = max|F^H(a exp(j psi))|^2 / max|F^H a|^2,
+ * psi = phi - phi_true with piston, tip and tilt removed over the pupil.
+ * phi_true: device pointer, N*N floats.  Synchronises; result in *S (host). */
+int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Group `count` streams (any mix of N) so that one call advances all of them
+ * by one frame.  Streams keep their own state and numerics: a stream gives
+ * the same result alone and in any batch.  flags: DDH_BATCH_GRAPH captures the
+ * per-frame launch sequence in a HIP graph on first use.  The batch does not
+ * own the streams; destroy the batch before its streams. */
+#define DDH_BATCH_GRAPH 1
+int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);
+int ddh_batch_destroy(ddh_batch_t b);
+
+/* One DDH frame on every stream of the batch.  y: host array of `count`
+ * device pointers (the i-th frame is for the i-th stream passed to
+ * ddh_batch_create); the host array may be reused once the call returns. */
+int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
+
+/* Per-kernel timing of the eager (non-graph) batch step: when enabled, each
+ * ddh_batch_step records HIP events around every kernel it launches.
+ * ddh_batch_stage_times synchronises and writes, for each kernel kind k < *n
+ * (on input *n is the capacity of the arrays), the summed milliseconds ms[k]
+ * and launch count calls[k] since timing was enabled, and its name to
+ * names[k] (static strings).  Kinds: 0 stats, 1 finalize, 2 row-ifft,
+ * 3 col-fused, 4 row-fft, 5 m-step, 6 set-y, 7 flip. */
+int ddh_batch_set_timing(ddh_batch_t b, int enable);
+int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
+
+/* ---------------------------------------------------------- FFT (a3, a6) */
+
+/* Batched unitary 2D DFT of `count` N x N complex64 images (device pointers,
+ * in and out may alias only if equal).  inverse = 0: kernel exp(-2 pi i k.n/N),
+ * inverse = 1: exp(+2 pi i k.n/N); both scaled by 1/N (Forward Model: F is a
+ * normalised DFT).  `work` is a device buffer of count*N*N complex64. */
+int ddh_fft2(int N, int count, const void* in, void* out, void* work, int inverse, void* hip_stream);
+
+/* ------------------------------------------------------------------- misc */
+const char* ddh_error_string(int code);
+/* Last HIP error message seen by the library (static storage). */
+const char* ddh_last_error_message(void);
+/* Library version string. */
+const char* ddh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDH_H */

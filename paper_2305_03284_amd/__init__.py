@@ -1,0 +1,281 @@
+"""Dynamic DH-MBIR (arXiv 2305.03284) per-frame EM step on AMD MI355X.
+
+Thin Python binding of the C ABI in ``include/ddh.h`` (``libddh.so``, built
+in-tree by ``paper_2305_03284_amd.build``).  Only argument marshalling lives
+here: every step of the path runs in the library's HIP kernels.  PyTorch is
+used for device memory and streams only.  There is no fallback: if the
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddh.so")
+
+DDH_OK = 0
+DDH_EINVAL = -1
+DDH_ENOMEM = -2
+DDH_EDEVICE = -3
+DDH_EDATA = -4
+DDH_ESTATE = -5
+DDH_BATCH_GRAPH = 1
+
+# every function the header declares, with its ctypes signature
+_c_int, _c_void_p, _c_double, _c_ll = ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``ddh_params``."""
+    _fields_ = [("N", ctypes.c_int), ("pupil_diameter", ctypes.c_float), ("lambda_", ctypes.c_float),
+                ("alpha", ctypes.c_float), ("n_k", ctypes.c_int), ("sigma_w2", ctypes.c_float),
+                ("qg_p", ctypes.c_float), ("qg_q", ctypes.c_float), ("qg_T", ctypes.c_float),
+                ("qg_sigma", ctypes.c_float), ("beta_phi", ctypes.c_float), ("r_floor", ctypes.c_float)]
+
+
+SIGNATURES = {
+    "ddh_default_params": (_c_int, [_c_int, ctypes.POINTER(Params)]),
+    "ddh_init_stream": (_c_int, [ctypes.POINTER(Params), _c_void_p, ctypes.POINTER(_c_void_p)]),
+    "ddh_destroy_stream": (_c_int, [_c_void_p]),
+    "ddh_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "ddh_em": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "ddh_get_phase": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "ddh_get_reflectance": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "ddh_set_state": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_ll, _c_void_p]),
+    "ddh_frame_count": (_c_int, [_c_void_p, ctypes.POINTER(_c_ll)]),
+    "ddh_status": (_c_int, [_c_void_p, _c_void_p]),
+    "ddh_get_params": (_c_int, [_c_void_p, ctypes.POINTER(Params)]),
+    "ddh_cost": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), _c_void_p]),
+    "ddh_strehl": (_c_int, [_c_void_p, _c_void_p, ctypes.POINTER(_c_double), _c_void_p]),
+    "ddh_batch_create": (_c_int, [ctypes.POINTER(_c_void_p), _c_int, _c_int, ctypes.POINTER(_c_void_p)]),
+    "ddh_batch_destroy": (_c_int, [_c_void_p]),
+    "ddh_batch_step": (_c_int, [_c_void_p, ctypes.POINTER(_c_void_p), _c_void_p]),
+    "ddh_batch_set_timing": (_c_int, [_c_void_p, _c_int]),
+    "ddh_batch_stage_times": (_c_int, [_c_void_p, ctypes.POINTER(_c_double), ctypes.POINTER(_c_ll),
+                                       ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_c_int)]),
+    "ddh_fft2": (_c_int, [_c_int, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p]),
+    "ddh_error_string": (ctypes.c_char_p, [_c_int]),
+    "ddh_last_error_message": (ctypes.c_char_p, []),
+    "ddh_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libddh.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_03284_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DDHError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = lib()
+        msg = L.ddh_error_string(code).decode()
+        detail = L.ddh_last_error_message().decode()
+        super().__init__(f"{where}: {msg} ({code})" + (f" [{detail}]" if detail and code == DDH_EDEVICE else ""))
+        self.code = code
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != DDH_OK:
+        raise DDHError(rc, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_params(N: int) -> Params:
+    p = Params()
+    _check(lib().ddh_default_params(N, ctypes.byref(p)), "ddh_default_params")
+    return p
+
+
+def make_params(N: int, **kw) -> Params:
+    """Params for grid N with keyword overrides (``lam`` for lambda)."""
+    p = default_params(N)
+    for k, v in kw.items():
+        k = "lambda_" if k in ("lam", "lambda") else k
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _check_frame(y, N):
+    torch = _torch()
+    if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.complex64
+            and tuple(y.shape) == (N, N) and y.is_contiguous()):
+        raise ValueError(f"frame must be a contiguous complex64 CUDA tensor of shape ({N}, {N})")
+
+
+class Stream:
+    """One DDH-MBIR stream with device-resident state (r, phi, n)."""
+
+    def __init__(self, N: int, params: Params | None = None, **kw):
+        self.N = N
+        self.params = params if params is not None else make_params(N, **kw)
+        h = ctypes.c_void_p()
+        _check(lib().ddh_init_stream(ctypes.byref(self.params), _stream_ptr(), ctypes.byref(h)), "ddh_init_stream")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise DDHError(DDH_ESTATE, "stream destroyed")
+        return self._h
+
+    def step(self, y) -> None:
+        """One DDH frame (Fig. 1 body) on the current torch stream."""
+        _check_frame(y, self.N)
+        _check(lib().ddh_step(self.handle, ctypes.c_void_p(y.data_ptr()), _stream_ptr()), "ddh_step")
+
+    def em(self, y) -> None:
+        """One plain EM(r, phi; y) iteration."""
+        _check_frame(y, self.N)
+        _check(lib().ddh_em(self.handle, ctypes.c_void_p(y.data_ptr()), _stream_ptr()), "ddh_em")
+
+    def phase(self):
+        torch = _torch()
+        out = torch.empty((self.N, self.N), dtype=torch.float32, device="cuda")
+        _check(lib().ddh_get_phase(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_ptr()), "ddh_get_phase")
+        return out
+
+    def reflectance(self):
+        torch = _torch()
+        out = torch.empty((self.N, self.N), dtype=torch.float32, device="cuda")
+        _check(lib().ddh_get_reflectance(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_ptr()),
+               "ddh_get_reflectance")
+        return out
+
+    def set_state(self, r, phi, n: int = 0) -> None:
+        torch = _torch()
+        for x in (r, phi):
+            if not (x.is_cuda and x.dtype == torch.float32 and tuple(x.shape) == (self.N, self.N) and x.is_contiguous()):
+                raise ValueError("state arrays must be contiguous float32 CUDA tensors of shape (N, N)")
+        _check(lib().ddh_set_state(self.handle, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                   int(n), _stream_ptr()), "ddh_set_state")
+
+    def frame_count(self) -> int:
+        n = ctypes.c_longlong()
+        _check(lib().ddh_frame_count(self.handle, ctypes.byref(n)), "ddh_frame_count")
+        return n.value
+
+    def status(self) -> int:
+        """DDH_OK or DDH_EDATA for the last submitted frame (synchronises)."""
+        rc = lib().ddh_status(self.handle, _stream_ptr())
+        if rc not in (DDH_OK, DDH_EDATA):
+            _check(rc, "ddh_status")
+        return rc
+
+    def cost(self, y) -> float:
+        _check_frame(y, self.N)
+        U = ctypes.c_double()
+        _check(lib().ddh_cost(self.handle, ctypes.c_void_p(y.data_ptr()), ctypes.byref(U), _stream_ptr()), "ddh_cost")
+        return U.value
+
+    def strehl(self, phi_true) -> float:
+        torch = _torch()
+        if not (phi_true.is_cuda and phi_true.dtype == torch.float32 and phi_true.is_contiguous()
+                and tuple(phi_true.shape) == (self.N, self.N)):
+            raise ValueError("phi_true must be a contiguous float32 CUDA tensor of shape (N, N)")
+        S = ctypes.c_double()
+        _check(lib().ddh_strehl(self.handle, ctypes.c_void_p(phi_true.data_ptr()), ctypes.byref(S), _stream_ptr()),
+               "ddh_strehl")
+        return S.value
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().ddh_destroy_stream(self._h), "ddh_destroy_stream")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several streams advanced together by one call per frame."""
+
+    def __init__(self, streams, graph: bool = True):
+        self.streams = list(streams)
+        arr = (ctypes.c_void_p * len(self.streams))(*[s.handle.value for s in self.streams])
+        h = ctypes.c_void_p()
+        _check(lib().ddh_batch_create(arr, len(self.streams), DDH_BATCH_GRAPH if graph else 0, ctypes.byref(h)),
+               "ddh_batch_create")
+        self._h = h
+        self._ptrs = (ctypes.c_void_p * len(self.streams))()
+
+    def step(self, ys) -> None:
+        if len(ys) != len(self.streams):
+            raise ValueError("one frame per stream")
+        for i, (y, s) in enumerate(zip(ys, self.streams)):
+            _check_frame(y, s.N)
+            self._ptrs[i] = y.data_ptr()
+        _check(lib().ddh_batch_step(self._h, self._ptrs, _stream_ptr()), "ddh_batch_step")
+
+    def step_ptrs(self, ptrs) -> None:
+        """Like step() with raw device pointers (already validated by the caller)."""
+        for i, p in enumerate(ptrs):
+            self._ptrs[i] = p
+        _check(lib().ddh_batch_step(self._h, self._ptrs, _stream_ptr()), "ddh_batch_step")
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().ddh_batch_set_timing(self._h, 1 if enable else 0), "ddh_batch_set_timing")
+
+    def stage_times(self) -> dict:
+        n = ctypes.c_int(16)
+        ms = (ctypes.c_double * 16)()
+        calls = (ctypes.c_longlong * 16)()
+        names = (ctypes.c_char_p * 16)()
+        _check(lib().ddh_batch_stage_times(self._h, ms, calls, names, ctypes.byref(n)), "ddh_batch_stage_times")
+        return {names[k].decode(): (ms[k], calls[k]) for k in range(n.value)}
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().ddh_batch_destroy(self._h), "ddh_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fft2(x, inverse: bool = False):
+    """Batched unitary 2-D DFT of a contiguous complex64 CUDA tensor (..., N, N)."""
+    torch = _torch()
+    if not (x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous() and x.shape[-1] == x.shape[-2]):
+        raise ValueError("fft2 needs a contiguous complex64 CUDA tensor (..., N, N)")
+    N = x.shape[-1]
+    count = x.numel() // (N * N)
+    out = torch.empty_like(x)
+    work = torch.empty_like(x)
+    _check(lib().ddh_fft2(N, count, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(work.data_ptr()), 1 if inverse else 0, _stream_ptr()), "ddh_fft2")
+    return out
+
+
+__all__ = ["Stream", "Batch", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+           "SIGNATURES", "LIB_PATH"]

@@ -1,0 +1,101 @@
+// Internal declarations shared by the kernel and runtime translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ddh {
+
+// Per-stream scalars written by the finalize kernel (float slots).
+enum ScalarSlot {
+  SC_MU_RE = 0,   // complex mean of y
+  SC_MU_IM = 1,
+  SC_SCALE = 2,   // sqrt(N^2) / ||y - mean||
+  SC_C0 = 3,      // least-squares plane over the pupil: c0 + c1*(i-c) + c2*(j-c)
+  SC_C1 = 4,
+  SC_C2 = 5,
+  SC_FLAG = 6,    // 1 = frame rejected (Normalize undefined)
+  SC_COUNT = 8
+};
+
+// Stats partials per block: mean_re, mean_im, M2, sum phi, sum (i-c) phi, sum (j-c) phi.
+constexpr int PART_STRIDE = 8;
+constexpr int STATS_PIX_PER_BLOCK = 4096;
+
+// Device-visible descriptor of one stream; an array of these (grouped by N)
+// lives in device memory for every plan.
+struct StreamDesc {
+  const float2* y;     // current frame (set per step)
+  float* r[2];         // ping-pong reflectance state
+  float* phi[2];       // ping-pong phase state
+  float2* T;           // row-pass output / (kappa, theta~) after the second row pass
+  float2* U;           // column-pass output
+  float* bb;           // |b|^2 from the column pass
+  float* part;         // stats partials, PART_STRIDE floats per stats block
+  float* scal;         // SC_COUNT floats
+  int N;
+  int cur;             // index of the current state buffer (advanced on the device)
+  float pupil_d2;      // diameter^2 (pixel (i,j) in pupil iff (2i-N+1)^2+(2j-N+1)^2 <= d2)
+  float sigma2, lam, alpha, beta, r_floor;
+  float qg_p, qg_q, qg_T, qg_sigma;
+  // precomputed QGGMRF constants
+  float qg_inv_sp;     // 1 / sigma^p
+  float qg_inv_Ts;     // 1 / (T sigma)
+  float qg_pmq;        // p - q
+  float qg_qop;        // q / p
+  float qg_pm2;        // p - 2
+  float pad1;
+  // pupil moments for the plane fit (exact, host-computed):
+  // n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with di = i-c, dj = j-c
+  double mom[6];
+};
+
+// Launch-site configuration (autotuned per N).
+struct TileConfig {
+  int row_lines;   // lines per workgroup in the row kernels
+  int col_width;   // columns per workgroup in the column kernel
+  int m_tile;      // output tile edge of the M-step kernel
+};
+
+// Kernel kinds for per-stage timing.
+enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_SETY, KK_COUNT };
+
+// Twiddle tables: exp(-2 pi i m / N) for m < N, for N = 64,128,256,512,
+// concatenated at offsets 0, 64, 192, 448 (total 960).
+int twiddle_offset(int N);
+constexpr int TWIDDLE_TOTAL = 960;
+
+// --- launch wrappers (defined in ddh_kernels.hip) ---------------------------
+// dptrs: device array of device descriptor pointers for the streams of one
+// launch (one grid size N for the per-N kernels).  k: EM iteration index
+// within the frame; the state buffer read is (cur + k) & 1.
+hipError_t launch_set_y(StreamDesc* const* dptrs, const float2* const* ys, int count, hipStream_t st);
+hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st);
+hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st);
+hipError_t launch_flip(StreamDesc* const* dptrs, int count, int nk, hipStream_t st);
+hipError_t launch_row1(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
+                       const TileConfig& tc, hipStream_t st);
+hipError_t launch_col(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int do_rinit,
+                      const TileConfig& tc, hipStream_t st);
+hipError_t launch_row2(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
+                       const TileConfig& tc, hipStream_t st);
+hipError_t launch_mstep(StreamDesc* const* dptrs, int count, int N, int k, int use_plane, int do_rinit,
+                        const TileConfig& tc, hipStream_t st);
+
+// Plain batched unitary 2D DFT (no fusion): rows into work, columns into out.
+hipError_t launch_fft2(int N, int count, const float2* in, float2* out, float2* work,
+                       const float2* tw, int inverse, hipStream_t st);
+
+// Diagnostics (FP64 reductions) on one stream; d is its device descriptor.
+hipError_t launch_backproject_cur(const StreamDesc* d, int N, int parity, const float2* tw,
+                                  float2* b, float2* work, hipStream_t st);
+hipError_t launch_cost_terms(const StreamDesc* d, int parity, const float2* b, double* partials,
+                             int nparts, hipStream_t st);
+hipError_t launch_strehl_sums(const StreamDesc* d, int parity, const float* phi_true,
+                              double* partials, int nparts, hipStream_t st);
+hipError_t launch_strehl_field(const StreamDesc* d, int N, int parity, const float* phi_true,
+                               const double* coef, float2* field, hipStream_t st);
+hipError_t launch_max_abs2(const float2* x, int n, double* partials, int nparts, hipStream_t st);
+hipError_t launch_fill_zero(float* p, long long n, hipStream_t st);
+hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st);
+
+}  // namespace ddh

@@ -1,0 +1,760 @@
+// Host runtime behind the C ABI in include/ddh.h: per-stream device state,
+// the per-frame launch sequence, HIP-graph capture, batches of streams with
+// mixed grid sizes, per-kernel event timing and the FP64 diagnostics.
+#include "ddh.h"
+#include "ddh_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace ddh;
+
+namespace {
+
+constexpr uint32_t kAlive = 0xDD4B1A5Eu;
+constexpr uint32_t kDead = 0xDEADDEADu;
+constexpr int kMaxDev = 64;
+constexpr int kDiagParts = 256;
+
+thread_local std::string g_last_err;
+std::mutex g_mu;
+float2* g_tw[kMaxDev] = {nullptr};
+
+int hip_fail(hipError_t e, const char* what) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  g_last_err = buf;
+  if (e == hipErrorOutOfMemory) return DDH_ENOMEM;
+  return DDH_EDEVICE;
+}
+#define DDH_CHECK(expr)                              \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_N(int N) { return N == 64 || N == 128 || N == 256 || N == 512; }
+
+int validate(const ddh_params* p) {
+  if (!p) return DDH_EINVAL;
+  if (!valid_N(p->N)) return DDH_EINVAL;
+  auto fin = [](float x) { return std::isfinite(x); };
+  if (!fin(p->pupil_diameter) || !(p->pupil_diameter > 0.f) || p->pupil_diameter > p->N * 1.41421357f) return DDH_EINVAL;
+  if (!fin(p->lambda) || p->lambda < 0.f || p->lambda > 1.f) return DDH_EINVAL;
+  if (!fin(p->alpha) || p->alpha < 0.f || p->alpha > 1.f) return DDH_EINVAL;
+  if (p->n_k < 1 || p->n_k > 1024) return DDH_EINVAL;
+  if (!fin(p->sigma_w2) || !(p->sigma_w2 > 0.f)) return DDH_EINVAL;
+  if (p->qg_p != 2.0f) return DDH_EINVAL;
+  if (!fin(p->qg_q) || p->qg_q < 1.f || p->qg_q > 2.f) return DDH_EINVAL;
+  if (!fin(p->qg_T) || !(p->qg_T > 0.f)) return DDH_EINVAL;
+  if (!fin(p->qg_sigma) || !(p->qg_sigma > 0.f)) return DDH_EINVAL;
+  if (!fin(p->beta_phi) || p->beta_phi < 0.f) return DDH_EINVAL;
+  if (!fin(p->r_floor) || !(p->r_floor > 0.f)) return DDH_EINVAL;
+  return DDH_OK;
+}
+
+// exp(-2 pi i m / N) tables for N = 64..512, computed in double.
+int ensure_twiddles(int dev, float2** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (dev < 0 || dev >= kMaxDev) return DDH_EDEVICE;
+  if (!g_tw[dev]) {
+    std::vector<float2> h(TWIDDLE_TOTAL);
+    for (int N : {64, 128, 256, 512}) {
+      const int off = twiddle_offset(N);
+      for (int m = 0; m < N; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)N;
+        h[off + m] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+    }
+    float2* d = nullptr;
+    DDH_CHECK(hipMalloc(&d, sizeof(float2) * TWIDDLE_TOTAL));
+    DDH_CHECK(hipMemcpy(d, h.data(), sizeof(float2) * TWIDDLE_TOTAL, hipMemcpyHostToDevice));
+    g_tw[dev] = d;
+  }
+  *out = g_tw[dev];
+  return DDH_OK;
+}
+
+TileConfig default_tiles(int N) {
+  switch (N) {
+    case 64: return {32, 32, 32};
+    case 128: return {32, 32, 32};
+    case 256: return {16, 16, 32};
+    default: return {8, 8, 32};
+  }
+}
+
+std::map<int, TileConfig>& tile_cache() {
+  static std::map<int, TileConfig> m;
+  return m;
+}
+
+TileConfig tiles_for(int N) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = tile_cache().find(N);
+  return it == tile_cache().end() ? default_tiles(N) : it->second;
+}
+
+const char* kKindNames[KK_COUNT + 1] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "set_y", "flip"};
+
+}  // namespace
+
+namespace ddh {
+int twiddle_offset(int N) {
+  switch (N) {
+    case 64: return 0;
+    case 128: return 64;
+    case 256: return 192;
+    case 512: return 448;
+    default: return -1;
+  }
+}
+}  // namespace ddh
+
+// ------------------------------------------------------------------ stream
+struct ddh_stream_s {
+  uint32_t magic = kAlive;
+  ddh_params prm{};
+  int N = 0;
+  int device = 0;
+  char* mem = nullptr;
+  StreamDesc h{};
+  StreamDesc* d = nullptr;       // device descriptor
+  StreamDesc** dptr = nullptr;   // device array holding d
+  double* diag = nullptr;        // device FP64 partials for diagnostics
+  float2* tw = nullptr;          // twiddles for this N on this device
+  int parity = 0;                // host mirror of d->cur
+  long long n = 0;
+  hipStream_t cap = nullptr;     // internal stream for graph capture
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = false;
+  bool alive() const { return magic == kAlive; }
+};
+
+// ------------------------------------------------------------------ batch
+struct Group {
+  int N;
+  int off;
+  int count;
+  TileConfig tc;
+  const float2* tw;
+};
+
+struct ddh_batch_s {
+  uint32_t magic = kAlive;
+  std::vector<ddh_stream_t> streams;  // input order
+  std::vector<int> pos;               // grouped position of input stream i
+  std::vector<Group> groups;
+  StreamDesc** dptrs = nullptr;       // device array, grouped order
+  int total = 0;
+  int n_k = 1;
+  int flags = 0;
+  int device = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const float2*> yord;
+  // timing
+  bool timing = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  double acc_ms[KK_COUNT + 1] = {0};
+  long long acc_n[KK_COUNT + 1] = {0};
+  bool alive() const { return magic == kAlive; }
+};
+
+namespace {
+
+// Enqueue one frame (mode 1: DDH frame with prologue; mode 0: plain EM) for
+// the streams in `dptrs` (grouped by N).  `ev` (optional) records events
+// around every launch.
+template <class OnLaunch>
+int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int total, int n_k, int mode,
+                  hipStream_t st, OnLaunch&& around) {
+  hipError_t e;
+  for (const Group& g : groups) {
+    e = around(KK_STATS, [&] { return launch_stats(dptrs + g.off, g.count, g.N, mode, st); });
+    if (e != hipSuccess) return hip_fail(e, "launch_stats");
+  }
+  e = around(KK_FINAL, [&] { return launch_finalize(dptrs, total, mode, st); });
+  if (e != hipSuccess) return hip_fail(e, "launch_finalize");
+  const int iters = mode ? n_k : 1;
+  for (int k = 0; k < iters; ++k) {
+    const int first = (mode && k == 0) ? 1 : 0;
+    for (const Group& g : groups) {
+      e = around(KK_ROW1, [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_row1");
+    }
+    for (const Group& g : groups) {
+      e = around(KK_COL, [&] { return launch_col(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_col");
+    }
+    for (const Group& g : groups) {
+      e = around(KK_ROW2, [&] { return launch_row2(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_row2");
+    }
+    for (const Group& g : groups) {
+      e = around(KK_MSTEP, [&] { return launch_mstep(dptrs + g.off, g.count, g.N, k, first, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_mstep");
+    }
+  }
+  e = around(KK_COUNT, [&] { return launch_flip(dptrs, total, iters, st); });
+  if (e != hipSuccess) return hip_fail(e, "launch_flip");
+  return DDH_OK;
+}
+
+struct NoTiming {
+  template <class F>
+  hipError_t operator()(int, F&& f) const { return f(); }
+};
+
+int check_stream(ddh_stream_t s) {
+  if (!s) return DDH_EINVAL;
+  if (!s->alive()) return DDH_ESTATE;
+  return DDH_OK;
+}
+
+int set_device_of(int dev) {
+  int cur = -1;
+  DDH_CHECK(hipGetDevice(&cur));
+  if (cur != dev) DDH_CHECK(hipSetDevice(dev));
+  return DDH_OK;
+}
+
+int single_step(ddh_stream_t s, const void* y, hipStream_t st, int mode) {
+  const float2* yp = static_cast<const float2*>(y);
+  hipError_t e = launch_set_y(s->dptr, &yp, 1, st);
+  if (e != hipSuccess) return hip_fail(e, "launch_set_y");
+  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
+  const int iters = mode ? s->prm.n_k : 1;
+  if (mode && s->use_graph) {
+    if (!s->gexec) {
+      hipGraph_t graph = nullptr;
+      DDH_CHECK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue_frame(s->dptr, g, 1, s->prm.n_k, 1, s->cap, NoTiming{});
+      hipError_t ec = hipStreamEndCapture(s->cap, &graph);
+      if (rc != DDH_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+      ec = hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ec != hipSuccess) {
+        s->gexec = nullptr;
+        return hip_fail(ec, "hipGraphInstantiate");
+      }
+    }
+    DDH_CHECK(hipGraphLaunch(s->gexec, st));
+  } else {
+    int rc = enqueue_frame(s->dptr, g, 1, s->prm.n_k, mode, st, NoTiming{});
+    if (rc != DDH_OK) return rc;
+  }
+  s->parity = (s->parity + iters) & 1;
+  if (mode) s->n++;
+  return DDH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ddh_version(void) { return "ddh-mi355x 0.1 (gfx950)"; }
+
+const char* ddh_error_string(int code) {
+  switch (code) {
+    case DDH_OK: return "ok";
+    case DDH_EINVAL: return "invalid argument";
+    case DDH_ENOMEM: return "out of device memory";
+    case DDH_EDEVICE: return "HIP runtime error";
+    case DDH_EDATA: return "frame rejected: Normalize undefined (zero or non-finite ||y - mean||)";
+    case DDH_ESTATE: return "invalid handle state";
+    default: return "unknown error";
+  }
+}
+
+const char* ddh_last_error_message(void) { return g_last_err.c_str(); }
+
+int ddh_default_params(int N, ddh_params* p) {
+  if (!p || !valid_N(N)) return DDH_EINVAL;
+  p->N = N;
+  p->pupil_diameter = (float)N;
+  p->lambda = 0.45f;
+  p->alpha = 0.025f;
+  p->n_k = 1;
+  p->sigma_w2 = 0.1f;
+  p->qg_p = 2.0f;
+  p->qg_q = 1.2f;
+  p->qg_T = 0.1f;
+  p->qg_sigma = 0.2f;
+  p->beta_phi = 0.5f;
+  p->r_floor = 1e-8f;
+  return DDH_OK;
+}
+
+int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
+  if (!out) return DDH_EINVAL;
+  int rc = validate(p);
+  if (rc != DDH_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  DDH_CHECK(hipGetDevice(&dev));
+  float2* tw_all = nullptr;
+  rc = ensure_twiddles(dev, &tw_all);
+  if (rc != DDH_OK) return rc;
+  const int N = p->N;
+  const size_t px = (size_t)N * N;
+  const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
+  // layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_r0 = take(px * 4), o_r1 = take(px * 4), o_p0 = take(px * 4), o_p1 = take(px * 4);
+  const size_t o_T = take(px * 8), o_U = take(px * 8), o_bb = take(px * 4);
+  const size_t o_part = take((size_t)nb * PART_STRIDE * 4), o_scal = take(SC_COUNT * 4);
+  const size_t o_desc = take(sizeof(StreamDesc)), o_dptr = take(sizeof(StreamDesc*));
+  const size_t o_diag = take(kDiagParts * 3 * sizeof(double) + 64);
+  char* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, off);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(stream)");
+  ddh_stream_t s = new ddh_stream_s();
+  s->prm = *p;
+  s->N = N;
+  s->device = dev;
+  s->mem = mem;
+  s->tw = tw_all + twiddle_offset(N);
+  StreamDesc& h = s->h;
+  h.y = nullptr;
+  h.r[0] = (float*)(mem + o_r0);
+  h.r[1] = (float*)(mem + o_r1);
+  h.phi[0] = (float*)(mem + o_p0);
+  h.phi[1] = (float*)(mem + o_p1);
+  h.T = (float2*)(mem + o_T);
+  h.U = (float2*)(mem + o_U);
+  h.bb = (float*)(mem + o_bb);
+  h.part = (float*)(mem + o_part);
+  h.scal = (float*)(mem + o_scal);
+  h.N = N;
+  h.cur = 0;
+  h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
+  h.sigma2 = p->sigma_w2;
+  h.lam = p->lambda;
+  h.alpha = p->alpha;
+  h.beta = p->beta_phi;
+  h.r_floor = p->r_floor;
+  h.qg_p = p->qg_p;
+  h.qg_q = p->qg_q;
+  h.qg_T = p->qg_T;
+  h.qg_sigma = p->qg_sigma;
+  h.qg_inv_sp = (float)(1.0 / ((double)p->qg_sigma * (double)p->qg_sigma));
+  h.qg_inv_Ts = (float)(1.0 / ((double)p->qg_T * (double)p->qg_sigma));
+  h.qg_pmq = p->qg_p - p->qg_q;
+  h.qg_qop = p->qg_q / p->qg_p;
+  h.qg_pm2 = p->qg_p - 2.0f;
+  // pupil moments (exact sums over integer coordinates, in double)
+  {
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    const double c = 0.5 * (N - 1);
+    const float d2 = h.pupil_d2;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const int di2 = 2 * i - N + 1, dj2 = 2 * j - N + 1;
+        if ((float)(di2 * di2 + dj2 * dj2) > d2) continue;
+        const double a = i - c, b = j - c;
+        m[0] += 1;
+        m[1] += a;
+        m[2] += b;
+        m[3] += a * a;
+        m[4] += a * b;
+        m[5] += b * b;
+      }
+    memcpy(h.mom, m, sizeof m);
+  }
+  s->d = (StreamDesc*)(mem + o_desc);
+  s->dptr = (StreamDesc**)(mem + o_dptr);
+  s->diag = (double*)(mem + o_diag);
+  auto fail = [&](int code) {
+    (void)hipFree(mem);
+    delete s;
+    return code;
+  };
+  e = hipMemcpy(s->d, &h, sizeof(StreamDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(desc)"));
+  StreamDesc* dv = s->d;
+  e = hipMemcpy(s->dptr, &dv, sizeof(StreamDesc*), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(dptr)"));
+  // r <- 0, phi <- 0 (Fig. 1) on the caller's stream; scratch zeroed too
+  e = launch_fill_zero((float*)mem, (long long)(o_T / 4), st);
+  if (e != hipSuccess) return fail(hip_fail(e, "fill_zero"));
+  e = launch_fill_zero((float*)(mem + o_part), (long long)((o_desc - o_part) / 4), st);
+  if (e != hipSuccess) return fail(hip_fail(e, "fill_zero"));
+  e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
+  const char* g = getenv("DDH_SINGLE_GRAPH");
+  s->use_graph = (g && g[0] == '1');
+  *out = s;
+  return DDH_OK;
+}
+
+int ddh_destroy_stream(ddh_stream_t s) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  set_device_of(s->device);
+  (void)hipDeviceSynchronize();
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
+  (void)hipFree(s->mem);
+  s->magic = kDead;
+  delete s;
+  return DDH_OK;
+}
+
+int ddh_get_params(ddh_stream_t s, ddh_params* out) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!out) return DDH_EINVAL;
+  *out = s->prm;
+  return DDH_OK;
+}
+
+int ddh_frame_count(ddh_stream_t s, long long* n) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!n) return DDH_EINVAL;
+  *n = s->n;
+  return DDH_OK;
+}
+
+int ddh_step(ddh_stream_t s, const void* y, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!y) return DDH_EINVAL;
+  return single_step(s, y, static_cast<hipStream_t>(hip_stream), 1);
+}
+
+int ddh_em(ddh_stream_t s, const void* y, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!y) return DDH_EINVAL;
+  return single_step(s, y, static_cast<hipStream_t>(hip_stream), 0);
+}
+
+static int copy_state(ddh_stream_t s, float* out, bool phase, hipStream_t st) {
+  const float* src = phase ? s->h.phi[s->parity] : s->h.r[s->parity];
+  DDH_CHECK(hipMemcpyAsync(out, src, sizeof(float) * (size_t)s->N * s->N, hipMemcpyDeviceToDevice, st));
+  return DDH_OK;
+}
+
+int ddh_get_phase(ddh_stream_t s, float* out, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!out) return DDH_EINVAL;
+  return copy_state(s, out, true, static_cast<hipStream_t>(hip_stream));
+}
+
+int ddh_get_reflectance(ddh_stream_t s, float* out, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!out) return DDH_EINVAL;
+  return copy_state(s, out, false, static_cast<hipStream_t>(hip_stream));
+}
+
+int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!r || !phi || n < 0) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t bytes = sizeof(float) * (size_t)s->N * s->N;
+  DDH_CHECK(hipMemcpyAsync(s->h.r[s->parity], r, bytes, hipMemcpyDeviceToDevice, st));
+  DDH_CHECK(hipMemcpyAsync(s->h.phi[s->parity], phi, bytes, hipMemcpyDeviceToDevice, st));
+  s->n = n;
+  return DDH_OK;
+}
+
+int ddh_status(ddh_stream_t s, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  float flag = 0.f;
+  DDH_CHECK(hipMemcpyAsync(&flag, s->h.scal + SC_FLAG, sizeof(float), hipMemcpyDeviceToHost,
+                           static_cast<hipStream_t>(hip_stream)));
+  DDH_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  return flag != 0.f ? DDH_EDATA : DDH_OK;
+}
+
+// ------------------------------------------------------------ diagnostics
+int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!y || !U) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const float2* yp = static_cast<const float2*>(y);
+  hipError_t e = launch_set_y(s->dptr, &yp, 1, st);
+  if (e != hipSuccess) return hip_fail(e, "set_y");
+  e = launch_stats(s->dptr, 1, s->N, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "stats");
+  e = launch_finalize(s->dptr, 1, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "finalize");
+  // b into U, work in T (both are scratch between frames)
+  e = launch_backproject_cur(s->d, s->N, s->parity, s->tw, s->h.U, s->h.T, st);
+  if (e != hipSuccess) return hip_fail(e, "backproject");
+  e = launch_cost_terms(s->d, s->parity, s->h.U, s->diag, kDiagParts, st);
+  if (e != hipSuccess) return hip_fail(e, "cost_terms");
+  std::vector<double> part(kDiagParts);
+  float flag = 0.f;
+  DDH_CHECK(hipMemcpyAsync(part.data(), s->diag, sizeof(double) * kDiagParts, hipMemcpyDeviceToHost, st));
+  DDH_CHECK(hipMemcpyAsync(&flag, s->h.scal + SC_FLAG, sizeof(float), hipMemcpyDeviceToHost, st));
+  DDH_CHECK(hipStreamSynchronize(st));
+  if (flag != 0.f) return DDH_EDATA;
+  double acc = 0.0;
+  for (double v : part) acc += v;
+  *U = acc;
+  return DDH_OK;
+}
+
+int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!phi_true || !S) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int N = s->N;
+  hipError_t e = launch_strehl_sums(s->d, s->parity, phi_true, s->diag, kDiagParts, st);
+  if (e != hipSuccess) return hip_fail(e, "strehl_sums");
+  std::vector<double> part(kDiagParts * 3);
+  DDH_CHECK(hipMemcpyAsync(part.data(), s->diag, sizeof(double) * kDiagParts * 3, hipMemcpyDeviceToHost, st));
+  DDH_CHECK(hipStreamSynchronize(st));
+  double rhs[3] = {0, 0, 0};
+  for (int b = 0; b < kDiagParts; ++b)
+    for (int k = 0; k < 3; ++k) rhs[k] += part[b * 3 + k];
+  const double* m = s->h.mom;
+  const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+  const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
+  double coef[3] = {0, 0, 0};
+  if (det != 0.0) {
+    const double s0 = rhs[0], s1 = rhs[1], s2 = rhs[2];
+    coef[0] = (s0 * (a11 * a22 - a12 * a12) - a01 * (s1 * a22 - a12 * s2) + a02 * (s1 * a12 - a11 * s2)) / det;
+    coef[1] = (a00 * (s1 * a22 - a12 * s2) - s0 * (a01 * a22 - a12 * a02) + a02 * (a01 * s2 - s1 * a02)) / det;
+    coef[2] = (a00 * (a11 * s2 - s1 * a12) - a01 * (a01 * s2 - s1 * a02) + s0 * (a01 * a12 - a11 * a02)) / det;
+  }
+  double* dcoef = s->diag + kDiagParts * 3;
+  DDH_CHECK(hipMemcpyAsync(dcoef, coef, sizeof coef, hipMemcpyHostToDevice, st));
+  double peak[2];
+  for (int pass = 0; pass < 2; ++pass) {
+    e = launch_strehl_field(s->d, N, s->parity, pass == 0 ? phi_true : nullptr, dcoef, s->h.U, st);
+    if (e != hipSuccess) return hip_fail(e, "strehl_field");
+    e = launch_fft2(N, 1, s->h.U, s->h.U, s->h.T, s->tw, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "fft2");
+    e = launch_max_abs2(s->h.U, N * N, s->diag, kDiagParts, st);
+    if (e != hipSuccess) return hip_fail(e, "max_abs2");
+    std::vector<double> mx(kDiagParts);
+    DDH_CHECK(hipMemcpyAsync(mx.data(), s->diag, sizeof(double) * kDiagParts, hipMemcpyDeviceToHost, st));
+    DDH_CHECK(hipStreamSynchronize(st));
+    peak[pass] = *std::max_element(mx.begin(), mx.end());
+  }
+  *S = peak[0] / peak[1];
+  return DDH_OK;
+}
+
+// ----------------------------------------------------------------- batches
+int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out) {
+  if (!streams || count <= 0 || !out) return DDH_EINVAL;
+  int dev = -1, n_k = -1;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_stream(streams[i]);
+    if (rc != DDH_OK) return rc;
+    if (dev < 0) dev = streams[i]->device;
+    if (streams[i]->device != dev) return DDH_ESTATE;
+    if (n_k < 0) n_k = streams[i]->prm.n_k;
+    if (streams[i]->prm.n_k != n_k) return DDH_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == streams[i]) return DDH_EINVAL;
+  }
+  ddh_batch_t b = new ddh_batch_s();
+  b->streams.assign(streams, streams + count);
+  b->total = count;
+  b->n_k = n_k;
+  b->flags = flags;
+  b->device = dev;
+  b->pos.assign(count, -1);
+  std::vector<StreamDesc*> order;
+  for (int N : {64, 128, 256, 512}) {
+    Group g{N, (int)order.size(), 0, tiles_for(N), nullptr};
+    for (int i = 0; i < count; ++i) {
+      if (streams[i]->N != N) continue;
+      b->pos[i] = (int)order.size();
+      order.push_back(streams[i]->d);
+      g.count++;
+      g.tw = streams[i]->tw;
+    }
+    if (g.count) b->groups.push_back(g);
+  }
+  b->yord.assign(count, nullptr);
+  hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipMalloc(batch)");
+  }
+  e = hipMemcpy(b->dptrs, order.data(), sizeof(StreamDesc*) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    (void)hipFree(b->dptrs);
+    delete b;
+    return hip_fail(e, "batch setup");
+  }
+  *out = b;
+  return DDH_OK;
+}
+
+int ddh_batch_destroy(ddh_batch_t b) {
+  if (!b) return DDH_EINVAL;
+  if (!b->alive()) return DDH_ESTATE;
+  set_device_of(b->device);
+  (void)hipDeviceSynchronize();
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipEvent_t ev : b->pool) (void)hipEventDestroy(ev);
+  (void)hipFree(b->dptrs);
+  b->magic = kDead;
+  delete b;
+  return DDH_OK;
+}
+
+int ddh_batch_set_timing(ddh_batch_t b, int enable) {
+  if (!b) return DDH_EINVAL;
+  if (!b->alive()) return DDH_ESTATE;
+  b->timing = enable != 0;
+  for (int k = 0; k <= KK_COUNT; ++k) {
+    b->acc_ms[k] = 0;
+    b->acc_n[k] = 0;
+  }
+  b->recs.clear();
+  b->pool_used = 0;
+  return DDH_OK;
+}
+
+static hipEvent_t pool_event(ddh_batch_t b) {
+  if (b->pool_used == b->pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    b->pool.push_back(ev);
+  }
+  return b->pool[b->pool_used++];
+}
+
+static int drain_timing(ddh_batch_t b) {
+  for (auto& r : b->recs) {
+    DDH_CHECK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    DDH_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    b->acc_ms[r.kind] += ms;
+    b->acc_n[r.kind] += 1;
+  }
+  b->recs.clear();
+  b->pool_used = 0;
+  return DDH_OK;
+}
+
+int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
+  if (!b || !y) return DDH_EINVAL;
+  if (!b->alive()) return DDH_ESTATE;
+  for (int i = 0; i < b->total; ++i) {
+    if (!b->streams[i]->alive()) return DDH_ESTATE;
+    if (!y[i]) return DDH_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < b->total; ++i) b->yord[b->pos[i]] = static_cast<const float2*>(y[i]);
+  if (b->timing && b->recs.size() > 4096) {
+    int rc = drain_timing(b);
+    if (rc != DDH_OK) return rc;
+  }
+  auto timed = [&](int kind, auto&& f) -> hipError_t {
+    if (!b->timing) return f();
+    hipEvent_t a = pool_event(b), c = pool_event(b);
+    if (!a || !c) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(c, st);
+    b->recs.push_back({kind, a, c});
+    return e;
+  };
+  hipError_t e = timed(KK_SETY, [&] { return launch_set_y(b->dptrs, b->yord.data(), b->total, st); });
+  if (e != hipSuccess) return hip_fail(e, "launch_set_y");
+  const bool graph = (b->flags & DDH_BATCH_GRAPH) && !b->timing;
+  if (graph) {
+    if (!b->gexec) {
+      hipGraph_t g = nullptr;
+      DDH_CHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, b->cap, NoTiming{});
+      hipError_t ec = hipStreamEndCapture(b->cap, &g);
+      if (rc != DDH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+      ec = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ec != hipSuccess) {
+        b->gexec = nullptr;
+        return hip_fail(ec, "hipGraphInstantiate");
+      }
+    }
+    DDH_CHECK(hipGraphLaunch(b->gexec, st));
+  } else {
+    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed);
+    if (rc != DDH_OK) return rc;
+  }
+  for (ddh_stream_t s : b->streams) {
+    s->parity = (s->parity + b->n_k) & 1;
+    s->n++;
+  }
+  return DDH_OK;
+}
+
+int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n) {
+  if (!b || !n) return DDH_EINVAL;
+  if (!b->alive()) return DDH_ESTATE;
+  int rc = drain_timing(b);
+  if (rc != DDH_OK) return rc;
+  const int m = std::min(*n, (int)KK_COUNT + 1);
+  for (int k = 0; k < m; ++k) {
+    if (ms) ms[k] = b->acc_ms[k];
+    if (calls) calls[k] = b->acc_n[k];
+    if (names) names[k] = kKindNames[k];
+  }
+  *n = m;
+  return DDH_OK;
+}
+
+// ------------------------------------------------------------------- FFT
+int ddh_fft2(int N, int count, const void* in, void* out, void* work, int inverse, void* hip_stream) {
+  if (!valid_N(N) || count <= 0 || !in || !out || !work) return DDH_EINVAL;
+  if (inverse != 0 && inverse != 1) return DDH_EINVAL;
+  int dev = 0;
+  DDH_CHECK(hipGetDevice(&dev));
+  float2* tw = nullptr;
+  int rc = ensure_twiddles(dev, &tw);
+  if (rc != DDH_OK) return rc;
+  hipError_t e = launch_fft2(N, count, static_cast<const float2*>(in), static_cast<float2*>(out),
+                             static_cast<float2*>(work), tw + twiddle_offset(N), inverse,
+                             static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "launch_fft2");
+  return DDH_OK;
+}
+
+}  // extern "C"
