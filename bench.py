@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark: batched DDH-MBIR EM step on one MI355X.
+
+Workload (default): 64 independent streams at N=256, one DDH frame per stream
+per step (N_k = 1, so one EM iteration per stream per step), all streams
+advanced by one graph-captured batched call.  Synthetic frozen-flow frames are
+generated on the host, uploaded once and cycled, so the inputs are resident in
+HBM when the timed region starts.
+
+Prints one JSON line with the throughput (EM iterations per second), the
+roofline position of the dominant kernel (HIP events around each launch of an
+eager step on the launch stream), the plain one-stream-at-a-time rate, frame
+latency percentiles of a single stream, mean Strehl, and the FP64 oracle timed
+on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--streams", type=int, default=64)
+    p.add_argument("--N", type=int, default=256)
+    p.add_argument("--workload", choices=["uniform", "mixed"], default="uniform")
+    p.add_argument("--frames", type=int, default=8, help="distinct frames per stream (cycled)")
+    p.add_argument("--timing-steps", type=int, default=20)
+    p.add_argument("--latency-frames", type=int, default=200)
+    p.add_argument("--plain-steps", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-frames", type=int, default=60)
+    p.add_argument("--no-extras", action="store_true", help="only the timed batched step (for profiling)")
+    p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
+    return p.parse_args()
+
+
+def make_inputs(specs, n_frames):
+    import ddh_synth as synth
+    sims = [synth.Stream(sp) for sp in specs]
+    frames = [[sm.frame(n) for n in range(n_frames)] for sm in sims]
+    return sims, frames
+
+
+def gpu_params(D, N, sigma_w2):
+    import ddh_synth as synth
+    v = synth.DEFAULT_PARAMS
+    return D.make_params(N, pupil_diameter=float(N), lam=v["lam"], alpha=v["alpha"], n_k=v["n_k"],
+                         sigma_w2=sigma_w2, qg_q=v["qg_q"], qg_T=v["qg_T"], qg_sigma=v["qg_sigma"],
+                         beta_phi=v["beta_phi"], r_floor=v["r_floor"])
+
+
+def kernel_bytes(N, fill):
+    """Algorithmic HBM bytes per launch-pixel of each kernel: the inputs its
+    definition must read and the outputs it must write (arrays used only on
+    the pupil counted with the pupil fill fraction)."""
+    f = fill
+    return {
+        "stats": 8 + 4 * f,                     # y; phi on the pupil
+        "row_ifft": 12 * f + 8,                 # y, phi on the pupil; T
+        "col_fused": 8 + 4 + 8 + 4,             # T, r; U, |b|^2
+        "row_fft": 8 + 12 * f + 8 * f,          # U; y, phi on the pupil; (kappa, theta~) on the pupil
+        "m_step": 4 + 4 + 12 * f + 4 + 4 * f,   # r, |b|^2, phi, (kappa, theta~); r, phi (pupil)
+    }
+
+
+def oracle_baseline(specs, frames, n_frames_cpu):
+    """FP64 oracle on the host: the first stream of the workload, frames
+    cycled as on the GPU, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ddh as O
+    import ddh_synth as synth
+    sp = specs[0]
+    st = synth.Stream(sp)
+    v = synth.DEFAULT_PARAMS
+    prm = O.Params(sigma_w2=st.sigma_w2, lam=v["lam"], alpha=v["alpha"], n_k=v["n_k"], qg_q=v["qg_q"],
+                   qg_T=v["qg_T"], qg_sigma=v["qg_sigma"], beta_phi=v["beta_phi"], r_floor=v["r_floor"])
+    a = O.aperture(sp.N)
+    r = np.zeros((sp.N, sp.N))
+    phi = np.zeros((sp.N, sp.N))
+    ys = [f.astype(np.complex128) for f in frames[0]]
+    with threadpool_limits(limits=1):
+        r, phi = O.ddh_frame(r, phi, ys[0], a, prm)  # warm-up
+        t0 = time.perf_counter()
+        for k in range(n_frames_cpu):
+            r, phi = O.ddh_frame(r, phi, ys[k % len(ys)], a, prm)
+        dt = time.perf_counter() - t0
+    return {"value": n_frames_cpu * prm.n_k / dt, "unit": "EM iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_frames_cpu} DDH frames (N_k={prm.n_k}) of one N={sp.N} stream of the workload, "
+                      f"FP64 NumPy, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); streams are independent, "
+              "so a multi-GPU run shards them with no communication", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    import paper_2305_03284_amd as D
+    import ddh_synth as synth
+
+    if args.workload == "uniform":
+        specs = synth.batch_specs(uniform_N=args.N, count=args.streams, config_id=2)
+        wl = f"{args.streams} streams x N={args.N}, batched DDH frame (N_k=1), frozen-flow synthetic"
+    else:
+        specs = synth.batch_specs(count=args.streams, config_id=2)
+        wl = f"{args.streams} streams, N in {{128,256,512}} at 2:5:1, batched DDH frame (N_k=1), frozen-flow synthetic"
+    t_gen = time.perf_counter()
+    sims, frames = make_inputs(specs, args.frames)
+    t_gen = time.perf_counter() - t_gen
+    S = len(specs)
+    px_total = sum(sp.N * sp.N for sp in specs)
+
+    tiles = {}
+    for n_ in sorted({sp.N for sp in specs}):
+        if args.tiles:
+            D.set_tiles(n_, [int(v) for v in args.tiles.split(",")])
+        elif not args.no_autotune:
+            D.autotune(n_, sum(1 for sp in specs if sp.N == n_))
+        tiles[n_] = D.get_tiles(n_)
+
+    dev_frames = [[torch.from_numpy(frames[i][k]).cuda() for i in range(S)] for k in range(args.frames)]
+    ptrs = [[t.data_ptr() for t in dev_frames[k]] for k in range(args.frames)]
+    streams = [D.Stream(sp.N, gpu_params(D, sp.N, sims[i].sigma_w2)) for i, sp in enumerate(specs)]
+    batch = D.Batch(streams, graph=True)
+    torch.cuda.synchronize()
+
+    step = 0
+    for _ in range(args.warmup):
+        batch.step_ptrs(ptrs[step % args.frames])
+        step += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.step_ptrs(ptrs[step % args.frames])
+        step += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = S * args.steps  # N_k = 1: one EM iteration per stream per step
+    value = iters / dt
+    ms_per_step = 1e3 * dt / args.steps
+
+    out = {
+        "metric": "EM iters/s (batched DDH-MBIR EM step)",
+        "value": round(value, 1),
+        "unit": "EM iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl, "streams": S, "N": args.N if args.workload == "uniform" else "mixed",
+                   "n_k": 1, "pixels_per_step": px_total, "frames_cycled": args.frames,
+                   "tiles": {str(k): v for k, v in tiles.items()}},
+    }
+
+    # calibration copy for the HBM byte counters: a plain 64 MiB copy of a
+    # source pushed out of the caches by 512 MiB of later writes
+    src = torch.empty(64 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    flush = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(2.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["calibration_copy_bytes"] = 64 * 2 ** 20
+    del src, dst, flush
+
+    if not args.no_extras:
+        # ---- per-kernel timing (eager step, HIP events around every launch on its stream)
+        batch.set_timing(True)
+        for _ in range(args.timing_steps):
+            batch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        st_times = batch.stage_times()
+        batch.set_timing(False)
+        torch.cuda.synchronize()
+        fill = float(synth.aperture(args.N).sum()) / args.N ** 2 if args.workload == "uniform" else 0.785
+        kb = kernel_bytes(args.N, fill)
+        kernels = {}
+        for name, (ms, calls) in st_times.items():
+            if calls == 0:
+                continue
+            avg_us = 1e3 * ms / calls
+            entry = {"avg_us": round(avg_us, 3), "launches": calls}
+            if name in kb and args.workload == "uniform":
+                byt = kb[name] * px_total
+                entry["alg_bytes"] = int(byt)
+                entry["GB_s"] = round(byt / (avg_us * 1e-6) / 1e9, 1)
+            kernels[name] = entry
+        eager_step_us = sum(v["avg_us"] for v in kernels.values())
+        dom = max((k for k in kernels if k in kb), key=lambda k: kernels[k]["avg_us"])
+        if "GB_s" in kernels[dom]:
+            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"], "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
+                               "traffic": None}
+        step_bytes_floor = 56 * px_total  # compulsory + one global round trip per 2-D FFT
+        step_bytes_alg = sum(kb[k] for k in kb) * px_total
+        out["kernels"] = kernels
+        out["step"] = {"graph_us": round(1e3 * ms_per_step, 2), "eager_sum_of_kernels_us": round(eager_step_us, 2),
+                       "floor_bytes": step_bytes_floor, "alg_bytes": int(step_bytes_alg),
+                       "floor_frac_of_hbm_peak": round(step_bytes_floor / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "alg_GB_s": round(step_bytes_alg / (ms_per_step * 1e-3) / 1e9, 1)}
+
+        # ---- plain form: the same streams one at a time through the single-stream call
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for k in range(args.plain_steps):
+            fk = dev_frames[step % args.frames]
+            for i in range(S):
+                streams[i].step(fk[i])
+            step += 1
+        torch.cuda.synchronize()
+        plain = S * args.plain_steps / (time.perf_counter() - tp)
+        out["plain_one_stream_at_a_time"] = {"value": round(plain, 1), "unit": "EM iters/s",
+                                             "batched_over_plain": round(value / plain, 2)}
+
+        # ---- latency of one stream (config-1 style: N=256, frames on the device)
+        sp1 = synth.config1_stream(N=args.N)
+        lat_frames = [torch.from_numpy(sp1.frame(n)).cuda() for n in range(16)]
+        s1 = D.Stream(args.N, gpu_params(D, args.N, sp1.sigma_w2))
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.latency_frames)]
+        for n in range(5):
+            s1.step(lat_frames[n % 16])
+        torch.cuda.synchronize()
+        for n, (ea, eb) in enumerate(evs):
+            ea.record()
+            s1.step(lat_frames[n % 16])
+            eb.record()
+            eb.synchronize()
+        lat = np.array([ea.elapsed_time(eb) * 1e3 for ea, eb in evs])
+        out["latency_us_single_stream"] = {"p50": round(float(np.percentile(lat, 50)), 2),
+                                           "p99": round(float(np.percentile(lat, 99)), 2), "N": args.N,
+                                           "frames": args.latency_frames,
+                                           "note": "device time per frame, y already on the device"}
+
+        # ---- Strehl of the batch against the truth of the frame index each
+        # stream saw last (frames are cycled, so this is indicative only)
+        strehls = []
+        for i in range(min(S, 16)):
+            truth = torch.from_numpy(sims[i].phase((step - 1) % args.frames).astype(np.float32)).cuda()
+            strehls.append(streams[i].strehl(truth))
+        out["strehl_mean_first16"] = round(float(np.mean(strehls)), 4)
+
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = oracle_baseline(specs, frames, args.cpu_frames)
+            out["cpu_baseline"]["host_cpu"] = _cpu_model()
+            out["cpu_baseline"]["host_cpu_count"] = os.cpu_count()
+    out["input_generation_s"] = round(t_gen, 1)
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -111,7 +111,8 @@ int ddh_get_phase(ddh_stream_t s, float* out, void* hip_stream);
 int ddh_get_reflectance(ddh_stream_t s, float* out, void* hip_stream);
 
 /* Overwrite the state (r, phi, n) from device pointers to N*N floats, for
- * checkpoint/resume.  r must be >= r_floor; phi should be zero off the pupil. */
+ * checkpoint/resume.  r must be >= r_floor; phi values off the pupil are
+ * ignored (stored as zero, as the state always holds them). */
 int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n, void* hip_stream);
 
 /* Frames submitted so far (n of Fig. 1). */
@@ -145,9 +146,15 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
 /* Group `count` streams (any mix of N) so that one call advances all of them
  * by one frame.  Streams keep their own state and numerics: a stream gives
  * the same result alone and in any batch.  flags: DDH_BATCH_GRAPH captures the
- * per-frame launch sequence in a HIP graph on first use.  The batch does not
- * own the streams; destroy the batch before its streams. */
+ * per-frame launch sequence in a HIP graph on first use; DDH_BATCH_LANES(n)
+ * (n = 1..8) splits the streams into n lanes balanced by pixel count whose
+ * launch chains run on n internal HIP streams forked from and joined back
+ * into the caller's stream, so that one lane's compute-bound M-step overlaps
+ * another lane's memory-bound FFT passes (a graph then has n parallel
+ * branches).  All n_k must be equal.  The batch does not own the streams;
+ * destroy the batch before its streams. */
 #define DDH_BATCH_GRAPH 1
+#define DDH_BATCH_LANES(n) (((n) & 0xff) << 8)
 int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);
 int ddh_batch_destroy(ddh_batch_t b);
 
@@ -162,7 +169,9 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * (on input *n is the capacity of the arrays), the summed milliseconds ms[k]
  * and launch count calls[k] since timing was enabled, and its name to
  * names[k] (static strings).  Kinds: 0 stats, 1 finalize, 2 row-ifft,
- * 3 col-fused, 4 row-fft, 5 m-step, 6 set-y, 7 flip. */
+ * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame pointers).  The combine
+ * of the stats partials runs inside the first row pass of a frame, so kind 1
+ * stays at zero launches in a batch step. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 
@@ -173,6 +182,28 @@ int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const cha
  * inverse = 1: exp(+2 pi i k.n/N); both scaled by 1/N (Forward Model: F is a
  * normalised DFT).  `work` is a device buffer of count*N*N complex64. */
 int ddh_fft2(int N, int count, const void* in, void* out, void* work, int inverse, void* hip_stream);
+
+/* ------------------------------------------------------------------ tiles */
+
+/* Launch tiling for grid size N: cfg[0] lines per workgroup of the row
+ * passes (4, 8, 16, 32), cfg[1] columns per workgroup of the column pass
+ * (4, 8, 16, 32), cfg[2] x cfg[3] output tile of the M-step (16x16, 16x32,
+ * 16x64, 32x32, 32x64, 64x64, 32x128; each side at most N), or 0 x 0 for
+ * four whole-image colour-pass launches instead of one halo-tiled kernel.  Tiling never changes results: every pixel is computed
+ * by the same arithmetic whichever workgroup computes it.  The setting is
+ * process-wide; it applies to batches created afterwards and to single-stream
+ * calls made afterwards (a single-stream graph keeps the tiling it was captured
+ * with).  DDH_EINVAL for an unsupported combination. */
+int ddh_set_tiles(int N, const int* cfg);
+int ddh_get_tiles(int N, int* cfg);
+
+/* Autotune the tiling for grid size N on the current device: time every
+ * candidate of each kernel on `count` temporary streams (synthetic frames
+ * generated on the device), keep the fastest per kernel, and install it as with
+ * ddh_set_tiles.  Writes the choice to cfg (4 ints) and the winners' average
+ * kernel times in microseconds to us (4 doubles: both row passes together,
+ * column pass, 0, M-step), either may be NULL.  Synchronises the device. */
+int ddh_autotune(int N, int count, int* cfg, double* us);
 
 /* ------------------------------------------------------------------- misc */
 const char* ddh_error_string(int code);

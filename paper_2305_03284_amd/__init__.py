@@ -55,6 +55,9 @@ SIGNATURES = {
     "ddh_batch_stage_times": (_c_int, [_c_void_p, ctypes.POINTER(_c_double), ctypes.POINTER(_c_ll),
                                        ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_c_int)]),
     "ddh_fft2": (_c_int, [_c_int, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p]),
+    "ddh_set_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
+    "ddh_get_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
+    "ddh_autotune": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)]),
     "ddh_error_string": (ctypes.c_char_p, [_c_int]),
     "ddh_last_error_message": (ctypes.c_char_p, []),
     "ddh_version": (ctypes.c_char_p, []),
@@ -217,12 +220,12 @@ class Stream:
 class Batch:
     """Several streams advanced together by one call per frame."""
 
-    def __init__(self, streams, graph: bool = True):
+    def __init__(self, streams, graph: bool = True, lanes: int = 1):
         self.streams = list(streams)
         arr = (ctypes.c_void_p * len(self.streams))(*[s.handle.value for s in self.streams])
         h = ctypes.c_void_p()
-        _check(lib().ddh_batch_create(arr, len(self.streams), DDH_BATCH_GRAPH if graph else 0, ctypes.byref(h)),
-               "ddh_batch_create")
+        flags = (DDH_BATCH_GRAPH if graph else 0) | ((int(lanes) & 0xff) << 8)
+        _check(lib().ddh_batch_create(arr, len(self.streams), flags, ctypes.byref(h)), "ddh_batch_create")
         self._h = h
         self._ptrs = (ctypes.c_void_p * len(self.streams))()
 
@@ -277,5 +280,26 @@ def fft2(x, inverse: bool = False):
     return out
 
 
-__all__ = ["Stream", "Batch", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+def set_tiles(N: int, cfg) -> None:
+    """Tiling for grid size N: (row lines, column width, M-step tile h, w)."""
+    arr = (ctypes.c_int * 4)(*cfg)
+    _check(lib().ddh_set_tiles(N, arr), "ddh_set_tiles")
+
+
+def get_tiles(N: int):
+    arr = (ctypes.c_int * 4)()
+    _check(lib().ddh_get_tiles(N, arr), "ddh_get_tiles")
+    return tuple(arr)
+
+
+def autotune(N: int, count: int):
+    """Time every tiling candidate on `count` temporary streams of size N,
+    install the fastest; returns (cfg, winner times in microseconds)."""
+    cfg = (ctypes.c_int * 4)()
+    us = (ctypes.c_double * 4)()
+    _check(lib().ddh_autotune(N, count, cfg, us), "ddh_autotune")
+    return tuple(cfg), tuple(us)
+
+
+__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

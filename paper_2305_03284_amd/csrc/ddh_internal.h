@@ -43,7 +43,7 @@ struct StreamDesc {
   float qg_pmq;        // p - q
   float qg_qop;        // q / p
   float qg_pm2;        // p - 2
-  float pad1;
+  int pending;         // buffer advance of the last frame, applied by the next k_begin
   // pupil moments for the plane fit (exact, host-computed):
   // n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with di = i-c, dj = j-c
   double mom[6];
@@ -53,11 +53,12 @@ struct StreamDesc {
 struct TileConfig {
   int row_lines;   // lines per workgroup in the row kernels
   int col_width;   // columns per workgroup in the column kernel
-  int m_tile;      // output tile edge of the M-step kernel
+  int m_tile_h;    // output tile height of the M-step kernel
+  int m_tile_w;    // output tile width of the M-step kernel
 };
 
 // Kernel kinds for per-stage timing.
-enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_SETY, KK_COUNT };
+enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_BEGIN, KK_COUNT };
 
 // Twiddle tables: exp(-2 pi i m / N) for m < N, for N = 64,128,256,512,
 // concatenated at offsets 0, 64, 192, 448 (total 960).
@@ -68,12 +69,11 @@ constexpr int TWIDDLE_TOTAL = 960;
 // dptrs: device array of device descriptor pointers for the streams of one
 // launch (one grid size N for the per-N kernels).  k: EM iteration index
 // within the frame; the state buffer read is (cur + k) & 1.
-hipError_t launch_set_y(StreamDesc* const* dptrs, const float2* const* ys, int count, hipStream_t st);
+hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, int count, int iters, hipStream_t st);
 hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st);
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st);
-hipError_t launch_flip(StreamDesc* const* dptrs, int count, int nk, hipStream_t st);
 hipError_t launch_row1(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
-                       const TileConfig& tc, hipStream_t st);
+                       int fin, int with_phi, const TileConfig& tc, hipStream_t st);
 hipError_t launch_col(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int do_rinit,
                       const TileConfig& tc, hipStream_t st);
 hipError_t launch_row2(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
@@ -96,6 +96,8 @@ hipError_t launch_strehl_field(const StreamDesc* d, int N, int parity, const flo
                                const double* coef, float2* field, hipStream_t st);
 hipError_t launch_max_abs2(const float2* x, int n, double* partials, int nparts, hipStream_t st);
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t st);
+hipError_t launch_synth_frames(float2* y, long long n, unsigned int seed, hipStream_t st);
 hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st);
+hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st);
 
 }  // namespace ddh

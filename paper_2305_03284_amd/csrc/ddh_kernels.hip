@@ -27,6 +27,15 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// sin and cos of x via v_sin_f32 / v_cos_f32 on x / (2 pi) reduced to
+// [-1/2, 1/2) revolutions (absolute error about 1e-6 for |x| below ~100 rad).
+__device__ __forceinline__ void fsincos(float x, float* sn, float* cs) {
+  float rev = x * 0.15915494309189534f;
+  rev -= rintf(rev);
+  *sn = __builtin_amdgcn_sinf(rev);
+  *cs = __builtin_amdgcn_cosf(rev);
+}
+
 // cos(2 pi q / 16) and sin(2 pi q / 16): the 16th roots of unity used by the
 // in-register DFTs, folded at compile time.
 __device__ __forceinline__ constexpr float cos16(int q) {
@@ -241,8 +250,8 @@ __device__ __forceinline__ bool in_pupil(int i, int j, int N, float d2) {
   return (float)(di * di + dj * dj) <= d2;
 }
 __device__ __forceinline__ float plane_at(const float* sc, int i, int j, int N) {
-  const float c = 0.5f * (float)(N - 1);
-  return sc[SC_C0] + sc[SC_C1] * ((float)i - c) + sc[SC_C2] * ((float)j - c);
+  const float cc = 0.5f * (float)(N - 1);
+  return __builtin_fmaf(sc[SC_C2], (float)j - cc, __builtin_fmaf(sc[SC_C1], (float)i - cc, sc[SC_C0]));
 }
 
 // Eq. (3) initialisation and E-step statistics, shared by k_col and k_mstep so
@@ -250,7 +259,7 @@ __device__ __forceinline__ float plane_at(const float* sc, int i, int j, int N) 
 __device__ __forceinline__ float rinit_of(float rp, float bb, float lam, float alpha, float floor_) {
   return fmaxf(__builtin_fmaf(1.0f - lam, rp, (lam * alpha) * bb), floor_);
 }
-__device__ __forceinline__ float wiener_of(float r, float s2) { return r / (r + s2); }
+__device__ __forceinline__ float wiener_of(float r, float s2) { return r * __builtin_amdgcn_rcpf(r + s2); }
 __device__ __forceinline__ float second_moment(float w, float bb, float s2) {
   // s = C + |mu|^2 = s2 w + w^2 |b|^2
   return __builtin_fmaf(s2, w, (w * w) * bb);
@@ -282,14 +291,21 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red /* >= NV*16
 }
 
 // ---------------------------------------------------------------------------
-// k_set_y: store this step's frame pointers into the stream descriptors
+// k_begin: start of a frame.  Store this step's frame pointers, apply the
+// state-buffer advance of the previous frame (its EM iteration count) and
+// record this frame's count for the next call.
 // ---------------------------------------------------------------------------
 struct YArgs {
   const float2* p[64];
 };
-__global__ void k_set_y(StreamDesc* const* dptrs, YArgs a, int count) {
+__global__ void k_begin(StreamDesc* const* dptrs, YArgs a, int count, int iters) {
   const int i = threadIdx.x;
-  if (i < count) dptrs[i]->y = a.p[i];
+  if (i < count) {
+    StreamDesc* d = dptrs[i];
+    d->y = a.p[i];
+    d->cur = (d->cur + d->pending) & 1;
+    d->pending = iters;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,16 +313,26 @@ __global__ void k_set_y(StreamDesc* const* dptrs, YArgs a, int count) {
 // registers), and the plane-fit sums of phi over the pupil.
 // grid (N*N/4096, streams), block 256
 // ---------------------------------------------------------------------------
+template <int N>
 __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int with_phi) {
   const StreamDesc& D = *dptrs[blockIdx.y];
   __shared__ float red[6 * 16];
-  const int N = D.N;
   const int base = blockIdx.x * STATS_PIX_PER_BLOCK;
+  constexpr float c = 0.5f * (float)(N - 1);
   float2 v[16];
+  float ph[16];
+  const float* phi = D.phi[D.cur];
+  // every global read is issued up front: y, and phi on the pupil
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = D.y[base + k * 256 + threadIdx.x];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int idx = base + k * 256 + threadIdx.x;
+    ph[k] = (with_phi && in_pupil(idx / N, idx % N, N, D.pupil_d2)) ? phi[idx] : 0.0f;
+  }
   float s[2] = {0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    v[k] = D.y[base + k * 256 + threadIdx.x];
     s[0] += v[k].x;
     s[1] += v[k].y;
   }
@@ -321,18 +347,14 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int wit
   block_sum<1>(m2, red);
   float ps[3] = {0.f, 0.f, 0.f};
   if (with_phi) {
-    const float* phi = D.phi[D.cur];
-    const float c = 0.5f * (float)(N - 1);
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int idx = base + k * 256 + threadIdx.x;
-      const int i = idx / N, j = idx - (idx / N) * N;
-      if (in_pupil(i, j, N, D.pupil_d2)) {
-        const float p = phi[idx];
-        ps[0] += p;
-        ps[1] += ((float)i - c) * p;
-        ps[2] += ((float)j - c) * p;
-      }
+      const int i = idx / N, j = idx % N;
+      const float p = ph[k];  // zero off the pupil
+      ps[0] += p;
+      ps[1] += ((float)i - c) * p;
+      ps[2] += ((float)j - c) * p;
     }
     block_sum<3>(ps, red);
   }
@@ -348,38 +370,34 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int wit
 }
 
 // ---------------------------------------------------------------------------
-// k_finalize: combine the block partials (fixed order, FP64 combine of a few
-// dozen values) into mean, scale, plane and the reject flag.  grid (streams)
+// Combine the stats partials of one stream (fixed order, FP64 combine of at
+// most 64 records by one wavefront) into mean, scale, plane coefficients and
+// the reject flag: out[SC_*].  Called by the first wave of a block.
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(StreamDesc* const* dptrs, int with_phi) {
-  if (threadIdx.x != 0) return;
-  const StreamDesc& D = *dptrs[blockIdx.x];
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ void combine_stats(const StreamDesc& D, int with_phi, float* out) {
+  const int lane = threadIdx.x & 63;
   const int N = D.N;
   const int nb = (N * N) / STATS_PIX_PER_BLOCK;
-  double mr = 0, mi = 0;
-  for (int b = 0; b < nb; ++b) {
-    mr += D.part[b * PART_STRIDE + 0];
-    mi += D.part[b * PART_STRIDE + 1];
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  if (lane < nb) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) p[q] = D.part[lane * PART_STRIDE + q];
   }
-  mr /= nb;
-  mi /= nb;
-  double m2 = 0, between = 0, s0 = 0, s1 = 0, s2 = 0;
-  for (int b = 0; b < nb; ++b) {
-    const float* p = D.part + b * PART_STRIDE;
-    m2 += p[2];
-    const double dr = p[0] - mr, di = p[1] - mi;
-    between += dr * dr + di * di;
-    s0 += p[3];
-    s1 += p[4];
-    s2 += p[5];
-  }
-  m2 += (double)STATS_PIX_PER_BLOCK * between;
+  const double mr = wave_sum_d(p[0]) / nb, mi = wave_sum_d(p[1]) / nb;
+  const double dr = lane < nb ? p[0] - mr : 0.0, di = lane < nb ? p[1] - mi : 0.0;
+  const double m2 = wave_sum_d(p[2]) + (double)STATS_PIX_PER_BLOCK * wave_sum_d(dr * dr + di * di);
+  const double s0 = wave_sum_d(p[3]), s1 = wave_sum_d(p[4]), s2 = wave_sum_d(p[5]);
+  if (lane != 0) return;
   const bool ok = (m2 > 0.0) && isfinite(m2) && isfinite(mr) && isfinite(mi);
-  float* sc = D.scal;
-  sc[SC_MU_RE] = (float)mr;
-  sc[SC_MU_IM] = (float)mi;
-  sc[SC_SCALE] = ok ? (float)sqrt((double)N * (double)N / m2) : 0.0f;
-  sc[SC_FLAG] = ok ? 0.0f : 1.0f;
+  out[SC_MU_RE] = (float)mr;
+  out[SC_MU_IM] = (float)mi;
+  out[SC_SCALE] = ok ? (float)sqrt((double)N * (double)N / m2) : 0.0f;
+  out[SC_FLAG] = ok ? 0.0f : 1.0f;
   double c0 = 0, c1 = 0, c2 = 0;
   if (with_phi) {
     // normal equations of the plane c0 + c1 di + c2 dj over the pupil (Cramer)
@@ -392,15 +410,15 @@ __global__ void k_finalize(StreamDesc* const* dptrs, int with_phi) {
       c2 = (a00 * (a11 * s2 - s1 * a12) - a01 * (a01 * s2 - s1 * a02) + s0 * (a01 * a12 - a11 * a02)) / det;
     }
   }
-  sc[SC_C0] = (float)c0;
-  sc[SC_C1] = (float)c1;
-  sc[SC_C2] = (float)c2;
+  out[SC_C0] = (float)c0;
+  out[SC_C1] = (float)c1;
+  out[SC_C2] = (float)c2;
 }
 
-// k_flip: after a frame of n_k EM iterations the current state buffer index advances by n_k.
-__global__ void k_flip(StreamDesc* const* dptrs, int count, int nk) {
-  const int i = threadIdx.x + blockIdx.x * blockDim.x;
-  if (i < count) dptrs[i]->cur = (dptrs[i]->cur + nk) & 1;
+// k_finalize: standalone combine (diagnostic path).  grid (streams), block 64
+__global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int with_phi) {
+  const StreamDesc& D = *dptrs[blockIdx.x];
+  combine_stats(D, with_phi, D.scal);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,36 +428,55 @@ __global__ void k_flip(StreamDesc* const* dptrs, int count, int nk) {
 // ---------------------------------------------------------------------------
 template <int N, int LPW>
 __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                             int k, int use_plane) {
+                                                             int k, int use_plane, int fin, int with_phi) {
   constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
+  __shared__ float2 s_tw[N];
+  __shared__ float scs[SC_COUNT];
   const StreamDesc& D = *dptrs[blockIdx.y];
-  const float* sc = D.scal;
-  if (sc[SC_FLAG] != 0.0f) return;
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
   const int row = blockIdx.x * LPW + line;
-  const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
-  const float scale = sc[SC_SCALE];
   const float* phi = D.phi[(D.cur + k) & 1] + row * N;
   const float2* y = D.y + row * N;
+  // global reads first (they depend on nothing computed here): the row of y
+  // and phi, and the twiddle table into LDS
+  float2 yv[E];
+  float phv[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int n = first_pos<N, +1>(i, t);
+    yv[i] = y[n];
+    phv[i] = phi[n];
+  }
+  for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
+  const float* sc = D.scal;
+  if (fin) {
+    // first EM iteration of a frame: every block combines the stats partials
+    // itself (identical arithmetic in all blocks); block 0 publishes them
+    if (threadIdx.x < 64) combine_stats(D, with_phi, scs);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) D.scal[threadIdx.x] = scs[threadIdx.x];
+    sc = scs;
+  }
+  if (sc[SC_FLAG] != 0.0f) return;
+  const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
+  const float scale = sc[SC_SCALE];
   float2 v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
-    const float2 yv = y[n];
-    const float ph = phi[n];
     if (in_pupil(row, n, N, D.pupil_d2)) {
-      const float p = use_plane ? ph - plane_at(sc, row, n, N) : ph;
+      const float p = use_plane ? phv[i] - plane_at(sc, row, n, N) : phv[i];
       float sn, cs;
-      sincosf(p, &sn, &cs);
-      const float2 yh = make_float2((yv.x - mu.x) * scale, (yv.y - mu.y) * scale);
+      fsincos(p, &sn, &cs);
+      const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
       v[i] = cmul(yh, make_float2(cs, -sn));
     } else {
       v[i] = make_float2(0.f, 0.f);
     }
   }
   RowLds<N> L{lds + line * RowLds<N>::STRIDE};
-  line_fft<N, +1>(v, t, L, tw);
+  line_fft<N, +1>(v, t, L, s_tw);
   float2* out = D.T + row * N;
 #pragma unroll
   for (int i = 0; i < E; ++i) out[last_pos<N, +1>(i, t)] = v[i];
@@ -454,34 +491,42 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 // ---------------------------------------------------------------------------
 template <int N, int W>
 __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                          int k, int do_rinit) {
+                                                          int k, int do_rinit, int mat) {
   constexpr int E = Plan<N>::E;
   __shared__ float2 lds[N * ColLds<W>::STRIDE];
+  __shared__ float2 s_tw[N];
   const StreamDesc& D = *dptrs[blockIdx.y];
-  if (D.scal[SC_FLAG] != 0.0f) return;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int col = blockIdx.x * W + w;
   float2 v[E];
+  float rpv[E];
+  const float* rin = D.r[(D.cur + k) & 1];
+  float* rmat = D.r[((D.cur + k) & 1) ^ 1];
+  // global reads first: the column, this thread's r values, the twiddles
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = D.T[first_pos<N, +1>(i, t) * N + col];
+#pragma unroll
+  for (int i = 0; i < E; ++i) rpv[i] = rin[last_pos<N, +1>(i, t) * N + col];
+  for (int i = threadIdx.x; i < N; i += W * (N / E)) s_tw[i] = tw[i];
+  if (D.scal[SC_FLAG] != 0.0f) return;
   ColLds<W> L{lds + w};
-  line_fft<N, +1>(v, t, L, tw);
+  line_fft<N, +1>(v, t, L, s_tw);
   const float invN = 1.0f / (float)N;
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor;
-  const float* rin = D.r[(D.cur + k) & 1];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = last_pos<N, +1>(i, t);
     const float2 b = cscale(v[i], invN);
     const float bb = b.x * b.x + b.y * b.y;
-    const float rp = rin[n * N + col];
+    const float rp = rpv[i];
     const float ri = do_rinit ? rinit_of(rp, bb, lam, alpha, fl) : rp;
     const float wgt = wiener_of(ri, s2);
     D.bb[n * N + col] = bb;
+    if (mat) rmat[n * N + col] = ri;  // the colour passes update this copy in place
     v[i] = cscale(b, wgt);
   }
   __syncthreads();
-  line_fft<N, -1>(v, t, L, tw);
+  line_fft<N, -1>(v, t, L, s_tw);
 #pragma unroll
   for (int i = 0; i < E; ++i) D.U[last_pos<N, -1>(i, t) * N + col] = v[i];
 }
@@ -495,51 +540,83 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
 // ---------------------------------------------------------------------------
 template <int N, int LPW>
 __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                             int k, int use_plane) {
+                                                             int k, int use_plane, int mat) {
   constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
+  __shared__ float2 s_tw[N];
   const StreamDesc& D = *dptrs[blockIdx.y];
   const float* sc = D.scal;
-  if (sc[SC_FLAG] != 0.0f) return;
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
   const int row = blockIdx.x * LPW + line;
+  for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
   float2 v[E];
   const float2* u = D.U + row * N;
+  const float* phi = D.phi[(D.cur + k) & 1] + row * N;
+  const float2* y = D.y + row * N;
+  // every global read is issued up front: the row, and y and phi at this
+  // thread's output positions that lie in the pupil
+  float2 yv[E];
+  float phv[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = u[first_pos<N, -1>(i, t)];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int m = last_pos<N, -1>(i, t);
+    yv[i] = make_float2(0.f, 0.f);
+    phv[i] = 0.f;
+    if (in_pupil(row, m, N, D.pupil_d2)) {
+      yv[i] = y[m];
+      phv[i] = phi[m];
+    }
+  }
+  if (sc[SC_FLAG] != 0.0f) return;
   RowLds<N> L{lds + line * RowLds<N>::STRIDE};
-  line_fft<N, -1>(v, t, L, tw);
+  line_fft<N, -1>(v, t, L, s_tw);
   const float invN = 1.0f / (float)N;
   const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
   const float scale = sc[SC_SCALE];
   const float c2s = 2.0f / D.sigma2;
-  const float* phi = D.phi[(D.cur + k) & 1] + row * N;
-  const float2* y = D.y + row * N;
   float2* out = D.T + row * N;
-  constexpr float kPi = 3.14159265358979323846f, k2Pi = 6.28318530717958647692f;
+  float* pmat = D.phi[((D.cur + k) & 1) ^ 1] + row * N;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int m = last_pos<N, -1>(i, t);
     float2 res = make_float2(0.f, 0.f);
     if (in_pupil(row, m, N, D.pupil_d2)) {
       const float2 z = cscale(v[i], invN);
-      const float2 yv = y[m];
-      const float2 yh = make_float2((yv.x - mu.x) * scale, (yv.y - mu.y) * scale);
-      const float p = use_plane ? phi[m] - plane_at(sc, row, m, N) : phi[m];
-      const float c = c2s * sqrtf(yh.x * yh.x + yh.y * yh.y) * sqrtf(z.x * z.x + z.y * z.y);
-      // yhat conj(z)
-      const float qr = yh.x * z.x + yh.y * z.y, qi = yh.y * z.x - yh.x * z.y;
-      const float theta = atan2f(qi, qr);
-      const float x = p - theta;
-      float x0 = x - k2Pi * floorf((x + kPi) * (1.0f / k2Pi));
-      if (x0 >= kPi) x0 -= k2Pi;
-      if (x0 < -kPi) x0 += k2Pi;
-      const float sinc = fabsf(x0) > 1e-4f ? sinf(x0) / x0 : 1.0f - x0 * x0 * (1.0f / 6.0f);
-      res = make_float2(c * sinc, p - x0);
+      const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
+      const float p = use_plane ? phv[i] - plane_at(sc, row, m, N) : phv[i];
+      // w = exp(j p) conj(yhat) z: |w| = |yhat||z| and arg w = p - theta, so
+      // x0 = arg w lies in (-pi, pi] already and c sin(x0) = (2/s2) Im w.
+      float sn, cs;
+      fsincos(p, &sn, &cs);
+      const float qr = yh.x * z.x + yh.y * z.y, qi = yh.x * z.y - yh.y * z.x;  // conj(yhat) z
+      const float wr = cs * qr - sn * qi, wi = sn * qr + cs * qi;
+      const float x0 = atan2f(wi, wr);
+      const float ka = fabsf(x0) > 1e-3f ? c2s * wi * __builtin_amdgcn_rcpf(x0)
+                                         : c2s * __builtin_amdgcn_sqrtf(wr * wr + wi * wi) * (1.0f - x0 * x0 * (1.0f / 6.0f));
+      res = make_float2(ka, p - x0);
+      if (mat) pmat[m] = p;  // the colour passes update this copy in place
     }
     out[m] = res;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Fast single-instruction math (v_rcp_f32, v_exp_f32, v_log_f32, v_sqrt_f32,
+// v_cos_f32: about 1 ulp on normal inputs).  Every cubic root found with them
+// is polished by Newton steps on the cubic itself, so their error does not
+// reach the result beyond a few ulp.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fcbrt(float x) {  // real cube root
+  const float m = fexp2(flog2(fabsf(x)) * (1.0f / 3.0f));
+  return copysignf(m, x);
+}
+__device__ __forceinline__ float fcos_rev(float rev) { return __builtin_amdgcn_cosf(rev); }  // cos(2 pi rev)
 
 // ---------------------------------------------------------------------------
 // r M-step pixel solve: global minimiser on (0, inf) of
@@ -554,83 +631,188 @@ __device__ __forceinline__ float cubic_f(float A, float B, float s, float x) {
   return __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A, x, -B), x, 1.0f), x, -s);
 }
 __device__ __forceinline__ float polish(float A, float B, float s, float x) {
+  float f = cubic_f(A, B, s, x);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    const float f = cubic_f(A, B, s, x);
     const float fp = __builtin_fmaf(__builtin_fmaf(3.0f * A, x, -2.0f * B), x, 1.0f);
-    if (fp != 0.0f) {
-      const float xn = x - f / fp;
-      if (xn > 0.0f && fabsf(cubic_f(A, B, s, xn)) < fabsf(f)) x = xn;
-    }
+    const float xn = x - f * frcp(fp);
+    const float fn = cubic_f(A, B, s, xn);
+    const bool take = (xn > 0.0f) && (fabsf(fn) < fabsf(f));
+    x = take ? xn : x;
+    f = take ? fn : f;
   }
   return x;
 }
-__device__ float solve_r(float s, float A, float B) {
+__device__ __forceinline__ float solve_r(float s, float A, float B) {
   if (!(A > 0.0f)) return s;
-  const float iA = 1.0f / A;
+  const float iA = frcp(A);
   const float a2 = -B * iA, a1 = iA, a0 = -s * iA;
   const float sh = -a2 * (1.0f / 3.0f);
   const float p = a1 - a2 * a2 * (1.0f / 3.0f);
   const float q = (2.0f / 27.0f) * a2 * a2 * a2 - a2 * a1 * (1.0f / 3.0f) + a0;
   const float disc = 0.25f * q * q + (1.0f / 27.0f) * p * p * p;
   if (disc >= 0.0f || p >= 0.0f) {
-    const float sq = sqrtf(fmaxf(disc, 0.0f));
-    const float u = cbrtf(-0.5f * q - copysignf(sq, q));
-    const float t = (u != 0.0f) ? u - p / (3.0f * u) : 0.0f;
+    const float sq = fsqrt(fmaxf(disc, 0.0f));
+    const float u = fcbrt(-0.5f * q - copysignf(sq, q));
+    const float t = (u != 0.0f) ? u - p * frcp(3.0f * u) : 0.0f;
     float x = t + sh;
     if (!(x > 0.0f) || !isfinite(x)) x = s;
     return polish(A, B, s, x);
   }
-  const float m = sqrtf(-p * (1.0f / 3.0f));
-  float arg = (1.5f * q / p) * sqrtf(-3.0f / p);
+  const float m = fsqrt(-p * (1.0f / 3.0f));
+  float arg = (1.5f * q * frcp(p)) * fsqrt(-3.0f * frcp(p));
   arg = fminf(1.0f, fmaxf(-1.0f, arg));
-  const float th = acosf(arg) * (1.0f / 3.0f);
-  constexpr float k2Pi3 = 2.09439510239319549231f;
-  float x1 = 2.0f * m * cosf(th) + sh;
-  float x2 = 2.0f * m * cosf(th - k2Pi3) + sh;
-  float x3 = 2.0f * m * cosf(th - 2.0f * k2Pi3) + sh;
-  // sort ascending
+  // th = acos(arg)/3 in revolutions
+  const float th = acosf(arg) * (1.0f / (6.0f * 3.14159265358979323846f));
+  const float x1 = 2.0f * m * fcos_rev(th) + sh;
+  const float x2 = 2.0f * m * fcos_rev(th - (1.0f / 3.0f)) + sh;
+  const float x3 = 2.0f * m * fcos_rev(th - (2.0f / 3.0f)) + sh;
   float lo = fminf(fminf(x1, x2), x3), hi = fmaxf(fmaxf(x1, x2), x3);
   if (!(lo > 0.0f)) lo = fminf(s, hi);
   lo = polish(A, B, s, lo);
   hi = polish(A, B, s, hi);
-  // h(lo) - h(hi)
-  const float dh = logf(lo / hi) + s * (hi - lo) / (lo * hi) + (lo - hi) * (0.5f * A * (lo + hi) - B);
+  // h(lo) - h(hi) as one difference
+  const float dh = 0.69314718055994531f * flog2(lo * frcp(hi)) + s * (hi - lo) * frcp(lo * hi) +
+                   (lo - hi) * (0.5f * A * (lo + hi) - B);
   return dh <= 0.0f ? lo : hi;
 }
 
 // rho'(d)/d of the QGGMRF prior for p = 2:
 //   (1/sig^2) (1 + (q/2) v) / (1 + v)^2,  v = |d/(T sig)|^(2-q)
-__device__ __forceinline__ float qg_weight(float d, float inv_sp, float inv_Ts, float pmq, float qop) {
-  const float ad = fabsf(d) * inv_Ts;
-  const float v = ad > 0.0f ? exp2f(pmq * log2f(ad)) : 0.0f;
+// (q = 2 gives v = 1 for every d, the quadratic prior.)  inv_sp is folded
+// into the neighbour weights by the caller.
+__device__ __forceinline__ float qg_shape(float d, float inv_Ts, float pmq, float qop) {
+  const float v = pmq > 0.0f ? fexp2(pmq * flog2(fabsf(d) * inv_Ts)) : 1.0f;
   const float den = 1.0f + v;
-  return inv_sp * __builtin_fmaf(qop, v, 1.0f) / (den * den);
+  return __builtin_fmaf(qop, v, 1.0f) * frcp(den * den);
 }
 
 // ---------------------------------------------------------------------------
-// k_mstep: one 4-colour sweep of the r and phi M-steps on a TS x TS output
-// tile.  The tile and a 4-pixel halo are staged in LDS; pass c updates the
-// colour-c pixels of the region shrunk by c+1, so the inner tile sees exactly
-// the values a whole-grid sweep produces.  Colour(i, j) = (i mod 2) + 2 (j mod 2).
-// Reads state buffer in = (cur + k) & 1, writes in ^ 1.
-// grid (tiles, streams), block 256; blocks are remapped so that neighbouring
-// tiles of a stream run on the same XCD (shared L2 for the halo).
+// Per-pixel M-step arithmetic shared by the halo-tiled kernel and the
+// whole-image colour passes, written with explicit FMAs so that both produce
+// bit-identical results.  Neighbour order: up, down, left, right, up-left,
+// up-right, down-left, down-right (edges weight 1/6, diagonals 1/12).
 // ---------------------------------------------------------------------------
-template <int N, int TS>
-__global__ __launch_bounds__(256) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane, int do_rinit) {
-  constexpr int RS = TS + 8;
-  constexpr int TPR = N / TS;          // tiles per row
-  constexpr int TILES = TPR * TPR;
-  __shared__ float sR[RS * RS], sS[RS * RS], sP[RS * RS], sK[RS * RS], sT[RS * RS];
-  // XCD-aware remap of the linear block id
+__device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, int j, int N) {
+  const float cc = 0.5f * (float)(N - 1);
+  return __builtin_fmaf(c2, (float)j - cc, __builtin_fmaf(c1, (float)i - cc, c0));
+}
+// r update of one pixel from its 8 neighbours (ok[e] = neighbour exists)
+__device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], const bool (&ok)[8], float inv_sp,
+                                         float inv_Ts, float pmq, float qop, float fl) {
+  float Ae = 0.f, Be = 0.f, Ad = 0.f, Bd = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float sh = ok[e] ? qg_shape(rp - rq[e], inv_Ts, pmq, qop) : 0.f;
+    if (e < 4) {
+      Ae += sh;
+      Be = __builtin_fmaf(sh, rq[e], Be);
+    } else {
+      Ad += sh;
+      Bd = __builtin_fmaf(sh, rq[e], Bd);
+    }
+  }
+  const float wE = inv_sp * (1.0f / 6.0f), wD = inv_sp * (1.0f / 12.0f);
+  const float A = __builtin_fmaf(wE, Ae, wD * Ad), B = __builtin_fmaf(wE, Be, wD * Bd);
+  return fmaxf(solve_r(s, A, B), fl);
+}
+// phi update of one pupil pixel; pq holds the neighbours' phases (zero off
+// the pupil and off the grid), P the prior weight of the pupil neighbours
+__device__ __forceinline__ float phi_pixel(const float (&pq)[8], float P, float ka, float tt, float beta2,
+                                           float cur) {
+  const float se = (pq[0] + pq[1]) + (pq[2] + pq[3]);
+  const float sd = (pq[4] + pq[5]) + (pq[6] + pq[7]);
+  const float Ph = __builtin_fmaf(1.0f / 6.0f, se, (1.0f / 12.0f) * sd);
+  const float den = __builtin_fmaf(beta2, P, ka);
+  return den > 0.0f ? __builtin_fmaf(ka, tt, beta2 * Ph) * frcp(den) : cur;
+}
+// prior weight of the pupil neighbours of a pupil pixel (di = 2i-N+1, dj = 2j-N+1)
+__device__ __forceinline__ float pupil_nbr_weight(int gi, int gj, int N, float d2) {
+  const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
+  const int ai = abs(di) + 2, aj = abs(dj) + 2;
+  if ((float)(ai * ai + aj * aj) <= d2) return 1.0f;  // farthest diagonal inside => all 8 inside
+  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+  float P = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ii = gi + nb[e][0], jj = gj + nb[e][1];
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N && in_pupil(ii, jj, N, d2)) P += e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f;
+  }
+  return P;
+}
+
+constexpr int MS_THREADS = 256;
+enum : unsigned char { F_GRID = 1, F_PUPIL = 2, F_INNER = 4, F_PFULL = 8 };
+
+// Geometry of the halo-tiled sweep: region RH x RW = (TH + 8) x (TW + 8);
+// pass c updates the colour-c pixels of rows/cols [c+1, R-c-1).  Tile origins
+// are even, so local parities equal global ones and everything is static.
+template <int TH, int TW>
+struct MsGeom {
+  static constexpr int RH = TH + 8, RW = TW + 8, RP = RH * RW;
+  static constexpr int li0(int c) { return (((c + 1) & 1) == (c & 1)) ? c + 1 : c + 2; }
+  static constexpr int lj0(int c) { return (((c + 1) & 1) == (c >> 1)) ? c + 1 : c + 2; }
+  static constexpr int nu(int c) { return (RH - c - 1 - li0(c) + 1) / 2; }
+  static constexpr int nv(int c) { return (RW - c - 1 - lj0(c) + 1) / 2; }
+  static constexpr int n(int c) { return nu(c) * nv(c); }
+  static constexpr int rounds(int c) { return (n(c) + MS_THREADS - 1) / MS_THREADS; }
+  static constexpr int slot0(int c) { return c == 0 ? 0 : slot0(c - 1) + rounds(c - 1); }
+  static constexpr int SLOTS = rounds(0) + rounds(1) + rounds(2) + rounds(3);
+  static __device__ __forceinline__ int offset(int c, int idx) {
+    const int u = idx / nv(c);
+    return (li0(c) + 2 * u) * RW + lj0(c) + 2 * (idx - u * nv(c));
+  }
+};
+
+template <int RW>
+__device__ __forceinline__ float r_update(const float* sR, const unsigned char* sF, int o, unsigned char f, float s,
+                                          float inv_sp, float inv_Ts, float pmq, float qop, float fl) {
+  constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
+  float rq[8];
+  bool ok[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    rq[e] = sR[o + offs[e]];
+    ok[e] = (f & F_INNER) ? true : (sF[o + offs[e]] & F_GRID) != 0;
+  }
+  return r_pixel(sR[o], s, rq, ok, inv_sp, inv_Ts, pmq, qop, fl);
+}
+
+template <int RW>
+__device__ __forceinline__ float phi_update(const float* sP, int o, float P, float ka, float tt, float beta2) {
+  constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
+  float pq[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) pq[e] = sP[o + offs[e]];
+  return phi_pixel(pq, P, ka, tt, beta2, sP[o]);
+}
+
+// ---------------------------------------------------------------------------
+// k_mstep: one 4-colour sweep of the r and phi M-steps on a TH x TW output
+// tile.  The tile and a 4-pixel halo of r and phi are staged in LDS; pass c
+// updates the colour-c pixels of the region shrunk by c+1, so the inner tile
+// sees exactly the values a whole-grid sweep produces.  Each thread keeps the
+// per-pixel constants (s, kappa, theta~) of the pixels it updates in
+// registers.  Colour(i, j) = (i mod 2) + 2 (j mod 2).  Reads state buffer
+// in = (cur + k) & 1, writes in ^ 1.  grid (tiles, streams), block 256; blocks
+// are remapped so that neighbouring tiles of a stream run on the same XCD
+// (shared L2 for the halo).
+// ---------------------------------------------------------------------------
+template <int N, int TH, int TW>
+__global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane, int do_rinit) {
+  using G = MsGeom<TH, TW>;
+  constexpr int RW = G::RW, RP = G::RP, SLOTS = G::SLOTS;
+  constexpr int TPC = N / TW, TPR = N / TH;
+  constexpr int TILES = TPC * TPR;
+  __shared__ float sR[RP], sP[RP];
+  __shared__ unsigned char sF[RP];
   const int total = TILES * gridDim.y;
   const int L = blockIdx.x + blockIdx.y * TILES;
   const int logical = (total % 8 == 0) ? (L % 8) * (total / 8) + (L / 8) : L;
   const int g = logical / TILES, tile = logical - g * TILES;
   const StreamDesc& D = *dptrs[g];
-  const int ti = tile / TPR, tj = tile - ti * TPR;
-  const int gi0 = ti * TS - 4, gj0 = tj * TS - 4;
+  const int ti = tile / TPC, tj = tile - ti * TPC;
+  const int gi0 = ti * TH - 4, gj0 = tj * TW - 4;
   const int in = (D.cur + k) & 1;
   const float* rin = D.r[in];
   const float* pin = D.phi[in];
@@ -638,105 +820,178 @@ __global__ __launch_bounds__(256) void k_mstep(StreamDesc* const* dptrs, int k, 
   float* pout = D.phi[in ^ 1];
   const float* sc = D.scal;
   const float d2 = D.pupil_d2;
+  const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
+  constexpr float cc = 0.5f * (float)(N - 1);
+  // ---- global reads for the pixels this thread updates, issued first
+  float ob[SLOTS], orp[SLOTS], okap[SLOTS], ott[SLOTS];
+  int oo[SLOTS];
+#define DDH_OWN(C)                                                           \
+  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {             \
+    const int slot = G::slot0(C) + rd;                                       \
+    const int idx = threadIdx.x + rd * MS_THREADS;                           \
+    ob[slot] = 0.f;                                                          \
+    orp[slot] = 0.f;                                                         \
+    okap[slot] = 0.f;                                                        \
+    ott[slot] = 0.f;                                                         \
+    oo[slot] = -1;                                                           \
+    if (idx < G::n(C)) {                                                     \
+      const int o = G::offset(C, idx);                                       \
+      const int li = o / RW, lj = o - (o / RW) * RW;                         \
+      const int gi = gi0 + li, gj = gj0 + lj;                                \
+      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {                          \
+        oo[slot] = o;                                                        \
+        const int pidx = gi * N + gj;                                        \
+        orp[slot] = rin[pidx];                                               \
+        ob[slot] = D.bb[pidx];                                               \
+        const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;                  \
+        if ((float)(di * di + dj * dj) <= d2) {                              \
+          const float2 kt = D.T[pidx];                                       \
+          okap[slot] = kt.x;                                                 \
+          ott[slot] = kt.y;                                                  \
+        }                                                                    \
+      }                                                                      \
+    }                                                                        \
+  }
+  DDH_OWN(0) DDH_OWN(1) DDH_OWN(2) DDH_OWN(3)
+#undef DDH_OWN
   if (sc[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
-    for (int idx = threadIdx.x; idx < TS * TS; idx += blockDim.x) {
-      const int gi = ti * TS + idx / TS, gj = tj * TS + idx % TS;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += MS_THREADS) {
+      const int gi = ti * TH + idx / TW, gj = tj * TW + idx % TW;
       rout[gi * N + gj] = rin[gi * N + gj];
       pout[gi * N + gj] = pin[gi * N + gj];
     }
     return;
   }
-  const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
-  for (int idx = threadIdx.x; idx < RS * RS; idx += blockDim.x) {
-    const int li = idx / RS, lj = idx - li * RS;
+  const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
+  // ---- stage the region: r after the Eq. (3) initialisation, phi' and flags
+  for (int idx = threadIdx.x; idx < RP; idx += MS_THREADS) {
+    const int li = idx / RW, lj = idx - li * RW;
     const int gi = gi0 + li, gj = gj0 + lj;
-    float r = 0.f, s = 0.f, p = 0.f, ka = 0.f, tt = 0.f;
+    float r = 0.f, p = 0.f;
+    unsigned char f = 0;
     if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
+      f = F_GRID;
+      if (gi >= 1 && gi <= N - 2 && gj >= 1 && gj <= N - 2) f |= F_INNER;
       const int pidx = gi * N + gj;
       const float rp = rin[pidx];
-      const float bb = D.bb[pidx];
-      r = do_rinit ? rinit_of(rp, bb, lam, alpha, fl) : rp;
-      s = second_moment(wiener_of(r, s2), bb, s2);
-      if (in_pupil(gi, gj, N, d2)) {
-        p = use_plane ? pin[pidx] - plane_at(sc, gi, gj, N) : pin[pidx];
-        const float2 kt = D.T[pidx];
-        ka = kt.x;
-        tt = kt.y;
+      r = do_rinit ? rinit_of(rp, D.bb[pidx], lam, alpha, fl) : rp;
+      const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
+      if ((float)(di * di + dj * dj) <= d2) {
+        f |= F_PUPIL;
+        // the farthest diagonal neighbour inside the disk => all 8 are
+        const int ai = abs(di) + 2, aj = abs(dj) + 2;
+        if ((float)(ai * ai + aj * aj) <= d2) f |= F_PFULL;
+        const float ph = pin[pidx];
+        p = use_plane ? ph - plane_val(c0, c1, c2, gi, gj, N) : ph;
       }
     }
     sR[idx] = r;
-    sS[idx] = s;
     sP[idx] = p;
-    sK[idx] = ka;
-    sT[idx] = tt;
+    sF[idx] = f;
+  }
+  // ---- s = E|g|^2 of the own pixels (same arithmetic as the staged r)
+  float os[SLOTS];
+#pragma unroll
+  for (int slot = 0; slot < SLOTS; ++slot) {
+    const float ri = do_rinit ? rinit_of(orp[slot], ob[slot], lam, alpha, fl) : orp[slot];
+    os[slot] = second_moment(wiener_of(ri, s2), ob[slot], s2);
   }
   __syncthreads();
   const float inv_sp = D.qg_inv_sp, inv_Ts = D.qg_inv_Ts, pmq = D.qg_pmq, qop = D.qg_qop;
-  constexpr float kE = 1.0f / 6.0f, kD = 1.0f / 12.0f;
-#pragma unroll 1
-  for (int c = 0; c < 4; ++c) {
-    const int lo = c + 1, hi = RS - c - 1;  // region [lo, hi)
-    const int pi_ = c & 1, pj_ = c >> 1;     // required parities of gi, gj
-    const int li0 = lo + (((gi0 + lo) & 1) != pi_);
-    const int lj0 = lo + (((gj0 + lo) & 1) != pj_);
-    const int nu = (hi - li0 + 1) >> 1, nv = (hi - lj0 + 1) >> 1;
-    for (int idx = threadIdx.x; idx < nu * nv; idx += blockDim.x) {
-      const int u = idx / nv;
-      const int li = li0 + 2 * u, lj = lj0 + 2 * (idx - u * nv);
-      const int gi = gi0 + li, gj = gj0 + lj;
-      if (gi < 0 || gi >= N || gj < 0 || gj >= N) continue;
-      const int o = li * RS + lj;
-      const bool up = gi > 0, dn = gi < N - 1, lf = gj > 0, rt = gj < N - 1;
-      // ---- r update
-      const float rp = sR[o];
-      float A = 0.f, B = 0.f;
-#define DDH_RNB(ok, off, bw)                                              \
-  if (ok) {                                                               \
-    const float rq = sR[o + (off)];                                       \
-    const float wq = (bw) * qg_weight(rp - rq, inv_sp, inv_Ts, pmq, qop); \
-    A += wq;                                                              \
-    B = __builtin_fmaf(wq, rq, B);                                        \
-  }
-      DDH_RNB(up, -RS, kE)
-      DDH_RNB(dn, RS, kE)
-      DDH_RNB(lf, -1, kE)
-      DDH_RNB(rt, 1, kE)
-      DDH_RNB(up && lf, -RS - 1, kD)
-      DDH_RNB(up && rt, -RS + 1, kD)
-      DDH_RNB(dn && lf, RS - 1, kD)
-      DDH_RNB(dn && rt, RS + 1, kD)
-#undef DDH_RNB
-      sR[o] = fmaxf(solve_r(sS[o], A, B), fl);
-      // ---- phi update (pupil pixels only; neighbours must be in the pupil)
-      if (in_pupil(gi, gj, N, d2)) {
-        float P = 0.f, Ph = 0.f;
-#define DDH_PNB(ok, di, dj, off, bw)                     \
-  if ((ok) && in_pupil(gi + (di), gj + (dj), N, d2)) { \
-    P += (bw);                                         \
-    Ph = __builtin_fmaf((bw), sP[o + (off)], Ph);      \
-  }
-        DDH_PNB(up, -1, 0, -RS, kE)
-        DDH_PNB(dn, 1, 0, RS, kE)
-        DDH_PNB(lf, 0, -1, -1, kE)
-        DDH_PNB(rt, 0, 1, 1, kE)
-        DDH_PNB(up && lf, -1, -1, -RS - 1, kD)
-        DDH_PNB(up && rt, -1, 1, -RS + 1, kD)
-        DDH_PNB(dn && lf, 1, -1, RS - 1, kD)
-        DDH_PNB(dn && rt, 1, 1, RS + 1, kD)
-#undef DDH_PNB
-        const float ka = sK[o];
-        const float den = ka + beta2 * P;
-        if (den > 0.0f) sP[o] = (ka * sT[o] + beta2 * Ph) / den;
-      }
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < TS * TS; idx += blockDim.x) {
-    const int li = 4 + idx / TS, lj = 4 + idx % TS;
+  // ---- the four colour passes (same-colour pixels are never neighbours, so
+  // each pass updates its pixels in place)
+#define DDH_PASS(C)                                                                                 \
+  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {                                    \
+    const int slot = G::slot0(C) + rd;                                                              \
+    const int o = oo[slot];                                                                         \
+    if (o >= 0) {                                                                                   \
+      const unsigned char f = sF[o];                                                                \
+      const float rn = r_update<RW>(sR, sF, o, f, os[slot], inv_sp, inv_Ts, pmq, qop, fl);          \
+      float pn = 0.f;                                                                               \
+      if (f & F_PUPIL) {                                                                            \
+        const int li = o / RW, lj = o - (o / RW) * RW;                                              \
+        const float P = (f & F_PFULL) ? 1.0f : pupil_nbr_weight(gi0 + li, gj0 + lj, N, d2);         \
+        pn = phi_update<RW>(sP, o, P, okap[slot], ott[slot], beta2);                                \
+      }                                                                                             \
+      sR[o] = rn;                                                                                   \
+      if (f & F_PUPIL) sP[o] = pn;                                                                  \
+    }                                                                                               \
+  }                                                                                                 \
+  __syncthreads();
+  DDH_PASS(0) DDH_PASS(1) DDH_PASS(2) DDH_PASS(3)
+#undef DDH_PASS
+  for (int idx = threadIdx.x; idx < TH * TW; idx += MS_THREADS) {
+    const int li = 4 + idx / TW, lj = 4 + idx % TW;
+    const int o = li * RW + lj;
     const int gi = gi0 + li, gj = gj0 + lj;
-    const int o = li * RS + lj;
     rout[gi * N + gj] = sR[o];
-    pout[gi * N + gj] = in_pupil(gi, gj, N, d2) ? sP[o] : 0.0f;
+    pout[gi * N + gj] = (sF[o] & F_PUPIL) ? sP[o] : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_mpass: one colour pass of the r and phi M-steps over whole images, one
+// thread per colour-C pixel.  The column pass has written r after the Eq. (3)
+// initialisation, and the second row pass phi', into the output state
+// buffers; pass C updates its pixels there in place (pixels of one colour are
+// never neighbours), reading the current neighbours through the caches.
+// grid (N*N/4/256, streams), block 256.
+// ---------------------------------------------------------------------------
+template <int N, int C>
+__global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) {
+  const StreamDesc& D = *dptrs[blockIdx.y];
+  constexpr int H = N / 2;
+  const int q = blockIdx.x * 256 + threadIdx.x;  // < N*N/4
+  const int u = q / H, v = q - (q / H) * H;
+  const int gi = 2 * u + (C & 1), gj = 2 * v + (C >> 1);
+  const int p = gi * N + gj;
+  const int in = (D.cur + k) & 1;
+  float* rw = D.r[in ^ 1];
+  float* pw = D.phi[in ^ 1];
+  const bool up = gi > 0, dn = gi < N - 1, lf = gj > 0, rt = gj < N - 1;
+  // global reads first
+  const float rp = rw[p];
+  const float bb = D.bb[p];
+  float rq[8];
+  rq[0] = up ? rw[p - N] : 0.f;
+  rq[1] = dn ? rw[p + N] : 0.f;
+  rq[2] = lf ? rw[p - 1] : 0.f;
+  rq[3] = rt ? rw[p + 1] : 0.f;
+  rq[4] = (up && lf) ? rw[p - N - 1] : 0.f;
+  rq[5] = (up && rt) ? rw[p - N + 1] : 0.f;
+  rq[6] = (dn && lf) ? rw[p + N - 1] : 0.f;
+  rq[7] = (dn && rt) ? rw[p + N + 1] : 0.f;
+  const float d2 = D.pupil_d2;
+  const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
+  const bool pup = (float)(di * di + dj * dj) <= d2;
+  float pq[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float2 kt = make_float2(0.f, 0.f);
+  if (pup) {
+    // off-pupil phases are zero in the buffer, so only the grid edge is masked
+    pq[0] = up ? pw[p - N] : 0.f;
+    pq[1] = dn ? pw[p + N] : 0.f;
+    pq[2] = lf ? pw[p - 1] : 0.f;
+    pq[3] = rt ? pw[p + 1] : 0.f;
+    pq[4] = (up && lf) ? pw[p - N - 1] : 0.f;
+    pq[5] = (up && rt) ? pw[p - N + 1] : 0.f;
+    pq[6] = (dn && lf) ? pw[p + N - 1] : 0.f;
+    pq[7] = (dn && rt) ? pw[p + N + 1] : 0.f;
+    kt = D.T[p];
+  }
+  if (D.scal[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
+    rw[p] = D.r[in][p];
+    pw[p] = D.phi[in][p];
+    return;
+  }
+  // ---- r update
+  const float s2 = D.sigma2;
+  const float s = second_moment(wiener_of(rp, s2), bb, s2);
+  const bool ok[8] = {up, dn, lf, rt, up && lf, up && rt, dn && lf, dn && rt};
+  rw[p] = r_pixel(rp, s, rq, ok, D.qg_inv_sp, D.qg_inv_Ts, D.qg_pmq, D.qg_qop, D.r_floor);
+  // ---- phi update
+  if (pup) {
+    const float P = pupil_nbr_weight(gi, gj, N, d2);
+    pw[p] = phi_pixel(pq, P, kt.x, kt.y, 2.0f * D.beta, pw[p]);
   }
 }
 
@@ -947,10 +1202,41 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1_cur(const StreamD
   for (int i = 0; i < E; ++i) work[row * N + last_pos<N, +1>(i, t)] = v[i];
 }
 
+// Deterministic pseudo-random complex frames for the autotuner (splitmix
+// hash of the element index; values uniform in [-1, 1) per component).
+__device__ __forceinline__ unsigned int mix32(unsigned int x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__global__ void k_synth_frames(float2* y, long long n, unsigned int seed) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const unsigned int h1 = mix32((unsigned int)i * 2u + seed), h2 = mix32((unsigned int)i * 2u + 1u + seed);
+    y[i] = make_float2((float)(h1 >> 8) * (2.0f / 16777216.0f) - 1.0f, (float)(h2 >> 8) * (2.0f / 16777216.0f) - 1.0f);
+  }
+}
+hipError_t launch_synth_frames(float2* y, long long n, unsigned int seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_synth_frames, dim3(1024), dim3(256), 0, st, y, n, seed);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_zero(float* p, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0.0f;
 }
+// phi with the off-pupil values set to zero (the state invariant)
+__global__ void k_copy_pupil(float* dst, const float* src, int N, float d2) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x)
+    dst[i] = in_pupil(i / N, i % N, N, d2) ? src[i] : 0.0f;
+}
+hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_pupil, dim3((N * N + 255) / 256), dim3(256), 0, st, dst, src, N, d2);
+  return hipGetLastError();
+}
+
 __global__ void k_copy(float* dst, const float* src, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -968,19 +1254,22 @@ __global__ void k_copy(float* dst, const float* src, long long n) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_set_y(StreamDesc* const* dptrs, const float2* const* ys, int count, hipStream_t st) {
+hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, int count, int iters, hipStream_t st) {
   for (int off = 0; off < count; off += 64) {
     YArgs a{};
     const int n = count - off < 64 ? count - off : 64;
     for (int i = 0; i < n; ++i) a.p[i] = ys[off + i];
-    hipLaunchKernelGGL(k_set_y, dim3(1), dim3(64), 0, st, dptrs + off, a, n);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, dptrs + off, a, n, iters);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st) {
-  hipLaunchKernelGGL(k_stats, dim3((N * N) / STATS_PIX_PER_BLOCK, count), dim3(256), 0, st, dptrs, with_phi);
+#define DDH_X(NN)                                                                                              \
+  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, count), dim3(256), 0, st, dptrs, with_phi); \
   return hipGetLastError();
+  DDH_DISPATCH_N(N, DDH_X)
+#undef DDH_X
 }
 
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st) {
@@ -988,18 +1277,15 @@ hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hi
   return hipGetLastError();
 }
 
-hipError_t launch_flip(StreamDesc* const* dptrs, int count, int nk, hipStream_t st) {
-  hipLaunchKernelGGL(k_flip, dim3((count + 63) / 64), dim3(64), 0, st, dptrs, count, nk);
-  return hipGetLastError();
-}
 
 template <int N>
-static hipError_t row1_n(StreamDesc* const* d, int count, const float2* tw, int k, int use_plane, int lpw,
-                         hipStream_t st) {
+static hipError_t row1_n(StreamDesc* const* d, int count, const float2* tw, int k, int use_plane, int fin,
+                         int with_phi, int lpw, hipStream_t st) {
   constexpr int T = N / Plan<N>::E;
-#define DDH_R1(L)                                                                                     \
-  case L:                                                                                             \
-    hipLaunchKernelGGL((k_row1<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane); \
+#define DDH_R1(L)                                                                                      \
+  case L:                                                                                              \
+    hipLaunchKernelGGL((k_row1<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, fin, \
+                       with_phi);                                                                       \
     break;
   switch (lpw) {
     DDH_R1(4) DDH_R1(8) DDH_R1(16) DDH_R1(32)
@@ -1009,12 +1295,12 @@ static hipError_t row1_n(StreamDesc* const* d, int count, const float2* tw, int 
   return hipGetLastError();
 }
 template <int N>
-static hipError_t row2_n(StreamDesc* const* d, int count, const float2* tw, int k, int use_plane, int lpw,
+static hipError_t row2_n(StreamDesc* const* d, int count, const float2* tw, int k, int use_plane, int mat, int lpw,
                          hipStream_t st) {
   constexpr int T = N / Plan<N>::E;
-#define DDH_R2(L)                                                                                     \
-  case L:                                                                                             \
-    hipLaunchKernelGGL((k_row2<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane); \
+#define DDH_R2(L)                                                                                          \
+  case L:                                                                                                  \
+    hipLaunchKernelGGL((k_row2<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, mat); \
     break;
   switch (lpw) {
     DDH_R2(4) DDH_R2(8) DDH_R2(16) DDH_R2(32)
@@ -1024,12 +1310,12 @@ static hipError_t row2_n(StreamDesc* const* d, int count, const float2* tw, int 
   return hipGetLastError();
 }
 template <int N>
-static hipError_t col_n(StreamDesc* const* d, int count, const float2* tw, int k, int do_rinit, int w,
+static hipError_t col_n(StreamDesc* const* d, int count, const float2* tw, int k, int do_rinit, int mat, int w,
                         hipStream_t st) {
   constexpr int T = N / Plan<N>::E;
-#define DDH_C(W)                                                                                    \
-  case W:                                                                                           \
-    hipLaunchKernelGGL((k_col<N, W>), dim3(N / W, count), dim3(W * T), 0, st, d, tw, k, do_rinit); \
+#define DDH_C(W)                                                                                         \
+  case W:                                                                                                \
+    hipLaunchKernelGGL((k_col<N, W>), dim3(N / W, count), dim3(W * T), 0, st, d, tw, k, do_rinit, mat); \
     break;
   switch (w) {
     DDH_C(4) DDH_C(8) DDH_C(16) DDH_C(32)
@@ -1039,20 +1325,27 @@ static hipError_t col_n(StreamDesc* const* d, int count, const float2* tw, int k
   return hipGetLastError();
 }
 template <int N>
-static hipError_t mstep_n(StreamDesc* const* d, int count, int k, int use_plane, int do_rinit, int ts,
+static hipError_t mstep_n(StreamDesc* const* d, int count, int k, int use_plane, int do_rinit, int th, int tw,
                           hipStream_t st) {
-#define DDH_M(TS)                                                                                          \
-  case TS:                                                                                                 \
-    if (N % TS) return hipErrorInvalidValue;                                                              \
-    hipLaunchKernelGGL((k_mstep<N, TS>), dim3((N / TS) * (N / TS), count), dim3(256), 0, st, d, k,      \
-                       use_plane, do_rinit);                                                               \
-    break;
-  switch (ts) {
-    DDH_M(16) DDH_M(32) DDH_M(64)
-    default: return hipErrorInvalidValue;
+  if (th == 0) {  // four whole-image colour passes
+    const dim3 grid((N * N / 4) / 256, count);
+    hipLaunchKernelGGL((k_mpass<N, 0>), grid, dim3(256), 0, st, d, k);
+    hipLaunchKernelGGL((k_mpass<N, 1>), grid, dim3(256), 0, st, d, k);
+    hipLaunchKernelGGL((k_mpass<N, 2>), grid, dim3(256), 0, st, d, k);
+    hipLaunchKernelGGL((k_mpass<N, 3>), grid, dim3(256), 0, st, d, k);
+    return hipGetLastError();
   }
+#define DDH_M(TH, TW)                                                                                          \
+  if (th == TH && tw == TW) {                                                                                  \
+    if constexpr (N % TH == 0 && N % TW == 0) {                                                                \
+      hipLaunchKernelGGL((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3(MS_THREADS), 0, st, d, k, \
+                         use_plane, do_rinit);                                                                 \
+      return hipGetLastError();                                                                                \
+    }                                                                                                          \
+  }
+  DDH_M(16, 16) DDH_M(16, 32) DDH_M(16, 64) DDH_M(32, 32) DDH_M(32, 64) DDH_M(64, 64) DDH_M(32, 128)
 #undef DDH_M
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 static bool lpw_ok(int N, int lpw) {
@@ -1064,30 +1357,30 @@ static bool w_ok(int N, int w) {
   return w * T <= 1024 && N % w == 0;
 }
 
-hipError_t launch_row1(StreamDesc* const* d, int count, int N, const float2* tw, int k, int use_plane,
-                       const TileConfig& tc, hipStream_t st) {
+hipError_t launch_row1(StreamDesc* const* d, int count, int N, const float2* tw, int k, int use_plane, int fin,
+                       int with_phi, const TileConfig& tc, hipStream_t st) {
   if (!lpw_ok(N, tc.row_lines)) return hipErrorInvalidValue;
-#define DDH_X(NN) return row1_n<NN>(d, count, tw, k, use_plane, tc.row_lines, st)
+#define DDH_X(NN) return row1_n<NN>(d, count, tw, k, use_plane, fin, with_phi, tc.row_lines, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
 }
 hipError_t launch_col(StreamDesc* const* d, int count, int N, const float2* tw, int k, int do_rinit,
                       const TileConfig& tc, hipStream_t st) {
   if (!w_ok(N, tc.col_width)) return hipErrorInvalidValue;
-#define DDH_X(NN) return col_n<NN>(d, count, tw, k, do_rinit, tc.col_width, st)
+#define DDH_X(NN) return col_n<NN>(d, count, tw, k, do_rinit, tc.m_tile_h == 0, tc.col_width, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
 }
 hipError_t launch_row2(StreamDesc* const* d, int count, int N, const float2* tw, int k, int use_plane,
                        const TileConfig& tc, hipStream_t st) {
   if (!lpw_ok(N, tc.row_lines)) return hipErrorInvalidValue;
-#define DDH_X(NN) return row2_n<NN>(d, count, tw, k, use_plane, tc.row_lines, st)
+#define DDH_X(NN) return row2_n<NN>(d, count, tw, k, use_plane, tc.m_tile_h == 0, tc.row_lines, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
 }
 hipError_t launch_mstep(StreamDesc* const* d, int count, int N, int k, int use_plane, int do_rinit,
                         const TileConfig& tc, hipStream_t st) {
-#define DDH_X(NN) return mstep_n<NN>(d, count, k, use_plane, do_rinit, tc.m_tile, st)
+#define DDH_X(NN) return mstep_n<NN>(d, count, k, use_plane, do_rinit, tc.m_tile_h, tc.m_tile_w, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
 }

@@ -85,10 +85,10 @@ int ensure_twiddles(int dev, float2** out) {
 
 TileConfig default_tiles(int N) {
   switch (N) {
-    case 64: return {32, 32, 32};
-    case 128: return {32, 32, 32};
-    case 256: return {16, 16, 32};
-    default: return {8, 8, 32};
+    case 64: return {32, 32, 32, 64};
+    case 128: return {32, 32, 32, 64};
+    case 256: return {16, 16, 32, 64};
+    default: return {8, 8, 32, 64};
   }
 }
 
@@ -97,13 +97,25 @@ std::map<int, TileConfig>& tile_cache() {
   return m;
 }
 
+bool tiles_ok(int N, const TileConfig& t) {
+  const int T = N / (N == 64 ? 8 : 16);
+  auto pow2in = [](int v) { return v == 4 || v == 8 || v == 16 || v == 32; };
+  if (!pow2in(t.row_lines) || !pow2in(t.col_width)) return false;
+  if (t.row_lines * T > 1024 || t.col_width * T > 1024 || N % t.row_lines || N % t.col_width) return false;
+  const bool ms = (t.m_tile_h == 0 && t.m_tile_w == 0) ||
+                  (t.m_tile_h == 16 && (t.m_tile_w == 16 || t.m_tile_w == 32 || t.m_tile_w == 64)) ||
+                  (t.m_tile_h == 32 && (t.m_tile_w == 32 || t.m_tile_w == 64 || t.m_tile_w == 128)) ||
+                  (t.m_tile_h == 64 && t.m_tile_w == 64);
+  return ms && (t.m_tile_h == 0 || (N % t.m_tile_h == 0 && N % t.m_tile_w == 0));
+}
+
 TileConfig tiles_for(int N) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = tile_cache().find(N);
   return it == tile_cache().end() ? default_tiles(N) : it->second;
 }
 
-const char* kKindNames[KK_COUNT + 1] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "set_y", "flip"};
+const char* kKindNames[KK_COUNT] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "begin"};
 
 }  // namespace
 
@@ -148,12 +160,23 @@ struct Group {
   const float2* tw;
 };
 
+// A lane is a subset of a batch's streams whose launch chain runs on its own
+// HIP stream, so that the chains of different lanes overlap on the device.
+struct Lane {
+  std::vector<Group> groups;
+  int off = 0, count = 0;
+  hipStream_t s = nullptr;
+  hipEvent_t join = nullptr;
+};
+
 struct ddh_batch_s {
   uint32_t magic = kAlive;
   std::vector<ddh_stream_t> streams;  // input order
   std::vector<int> pos;               // grouped position of input stream i
-  std::vector<Group> groups;
-  StreamDesc** dptrs = nullptr;       // device array, grouped order
+  std::vector<Group> groups;          // all groups (every lane), for timing mode
+  std::vector<Lane> lanes;
+  hipEvent_t fork = nullptr;
+  StreamDesc** dptrs = nullptr;       // device array, ordered by lane then N
   int total = 0;
   int n_k = 1;
   int flags = 0;
@@ -170,8 +193,8 @@ struct ddh_batch_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
-  double acc_ms[KK_COUNT + 1] = {0};
-  long long acc_n[KK_COUNT + 1] = {0};
+  double acc_ms[KK_COUNT] = {0};
+  long long acc_n[KK_COUNT] = {0};
   bool alive() const { return magic == kAlive; }
 };
 
@@ -188,13 +211,12 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
     e = around(KK_STATS, [&] { return launch_stats(dptrs + g.off, g.count, g.N, mode, st); });
     if (e != hipSuccess) return hip_fail(e, "launch_stats");
   }
-  e = around(KK_FINAL, [&] { return launch_finalize(dptrs, total, mode, st); });
-  if (e != hipSuccess) return hip_fail(e, "launch_finalize");
   const int iters = mode ? n_k : 1;
   for (int k = 0; k < iters; ++k) {
     const int first = (mode && k == 0) ? 1 : 0;
     for (const Group& g : groups) {
-      e = around(KK_ROW1, [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      e = around(KK_ROW1,
+                 [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, k == 0, mode, g.tc, st); });
       if (e != hipSuccess) return hip_fail(e, "launch_row1");
     }
     for (const Group& g : groups) {
@@ -210,8 +232,7 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
       if (e != hipSuccess) return hip_fail(e, "launch_mstep");
     }
   }
-  e = around(KK_COUNT, [&] { return launch_flip(dptrs, total, iters, st); });
-  if (e != hipSuccess) return hip_fail(e, "launch_flip");
+  (void)total;
   return DDH_OK;
 }
 
@@ -235,10 +256,10 @@ int set_device_of(int dev) {
 
 int single_step(ddh_stream_t s, const void* y, hipStream_t st, int mode) {
   const float2* yp = static_cast<const float2*>(y);
-  hipError_t e = launch_set_y(s->dptr, &yp, 1, st);
-  if (e != hipSuccess) return hip_fail(e, "launch_set_y");
-  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
   const int iters = mode ? s->prm.n_k : 1;
+  hipError_t e = launch_begin(s->dptr, &yp, 1, iters, st);
+  if (e != hipSuccess) return hip_fail(e, "launch_begin");
+  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
   if (mode && s->use_graph) {
     if (!s->gexec) {
       hipGraph_t graph = nullptr;
@@ -351,6 +372,7 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.scal = (float*)(mem + o_scal);
   h.N = N;
   h.cur = 0;
+  h.pending = 0;
   h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
   h.sigma2 = p->sigma_w2;
   h.lam = p->lambda;
@@ -481,7 +503,7 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const size_t bytes = sizeof(float) * (size_t)s->N * s->N;
   DDH_CHECK(hipMemcpyAsync(s->h.r[s->parity], r, bytes, hipMemcpyDeviceToDevice, st));
-  DDH_CHECK(hipMemcpyAsync(s->h.phi[s->parity], phi, bytes, hipMemcpyDeviceToDevice, st));
+  DDH_CHECK(launch_copy_pupil(s->h.phi[s->parity], phi, s->N, s->h.pupil_d2, st));
   s->n = n;
   return DDH_OK;
 }
@@ -503,8 +525,8 @@ int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream) {
   if (!y || !U) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const float2* yp = static_cast<const float2*>(y);
-  hipError_t e = launch_set_y(s->dptr, &yp, 1, st);
-  if (e != hipSuccess) return hip_fail(e, "set_y");
+  hipError_t e = launch_begin(s->dptr, &yp, 1, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "begin");
   e = launch_stats(s->dptr, 1, s->N, 0, st);
   if (e != hipSuccess) return hip_fail(e, "stats");
   e = launch_finalize(s->dptr, 1, 0, st);
@@ -583,6 +605,9 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
     for (int j = 0; j < i; ++j)
       if (streams[j] == streams[i]) return DDH_EINVAL;
   }
+  const int nl = (flags >> 8) & 0xff;
+  const int nlanes = std::max(1, std::min(nl == 0 ? 1 : nl, std::min(count, 8)));
+  if (nl > 8) return DDH_EINVAL;
   ddh_batch_t b = new ddh_batch_s();
   b->streams.assign(streams, streams + count);
   b->total = count;
@@ -590,17 +615,38 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
   b->flags = flags;
   b->device = dev;
   b->pos.assign(count, -1);
+  // assign streams to lanes: largest grids first, each to the lane with the
+  // fewest pixels so far (ties to the lowest lane)
+  std::vector<int> idx(count);
+  for (int i = 0; i < count; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return streams[a]->N > streams[c]->N; });
+  std::vector<long long> load(nlanes, 0);
+  std::vector<std::vector<int>> members(nlanes);
+  for (int i : idx) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[l].push_back(i);
+    load[l] += (long long)streams[i]->N * streams[i]->N;
+  }
   std::vector<StreamDesc*> order;
-  for (int N : {64, 128, 256, 512}) {
-    Group g{N, (int)order.size(), 0, tiles_for(N), nullptr};
-    for (int i = 0; i < count; ++i) {
-      if (streams[i]->N != N) continue;
-      b->pos[i] = (int)order.size();
-      order.push_back(streams[i]->d);
-      g.count++;
-      g.tw = streams[i]->tw;
+  b->lanes.resize(nlanes);
+  for (int l = 0; l < nlanes; ++l) {
+    Lane& ln = b->lanes[l];
+    ln.off = (int)order.size();
+    for (int N : {64, 128, 256, 512}) {
+      Group g{N, (int)order.size(), 0, tiles_for(N), nullptr};
+      for (int i : members[l]) {
+        if (streams[i]->N != N) continue;
+        b->pos[i] = (int)order.size();
+        order.push_back(streams[i]->d);
+        g.count++;
+        g.tw = streams[i]->tw;
+      }
+      if (g.count) {
+        ln.groups.push_back(g);
+        b->groups.push_back(g);
+      }
     }
-    if (g.count) b->groups.push_back(g);
+    ln.count = (int)order.size() - ln.off;
   }
   b->yord.assign(count, nullptr);
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
@@ -610,7 +656,18 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
   }
   e = hipMemcpy(b->dptrs, order.data(), sizeof(StreamDesc*) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && nlanes > 1) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int l = 0; l < nlanes && nlanes > 1 && e == hipSuccess; ++l) {
+    e = hipStreamCreateWithFlags(&b->lanes[l].s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->lanes[l].join, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
+    for (Lane& ln : b->lanes) {
+      if (ln.s) (void)hipStreamDestroy(ln.s);
+      if (ln.join) (void)hipEventDestroy(ln.join);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipFree(b->dptrs);
     delete b;
     return hip_fail(e, "batch setup");
@@ -626,6 +683,11 @@ int ddh_batch_destroy(ddh_batch_t b) {
   (void)hipDeviceSynchronize();
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (Lane& ln : b->lanes) {
+    if (ln.s) (void)hipStreamDestroy(ln.s);
+    if (ln.join) (void)hipEventDestroy(ln.join);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipEvent_t ev : b->pool) (void)hipEventDestroy(ev);
   (void)hipFree(b->dptrs);
   b->magic = kDead;
@@ -637,7 +699,7 @@ int ddh_batch_set_timing(ddh_batch_t b, int enable) {
   if (!b) return DDH_EINVAL;
   if (!b->alive()) return DDH_ESTATE;
   b->timing = enable != 0;
-  for (int k = 0; k <= KK_COUNT; ++k) {
+  for (int k = 0; k < KK_COUNT; ++k) {
     b->acc_ms[k] = 0;
     b->acc_n[k] = 0;
   }
@@ -668,6 +730,21 @@ static int drain_timing(ddh_batch_t b) {
   return DDH_OK;
 }
 
+// Fork the lanes off stream st, enqueue each lane's chain on its own stream,
+// join them back into st (capturable: the graph then has parallel branches).
+static int enqueue_lanes(ddh_batch_t b, hipStream_t st) {
+  if (b->lanes.size() == 1) return enqueue_frame(b->dptrs, b->lanes[0].groups, b->lanes[0].count, b->n_k, 1, st, NoTiming{});
+  DDH_CHECK(hipEventRecord(b->fork, st));
+  for (Lane& ln : b->lanes) {
+    DDH_CHECK(hipStreamWaitEvent(ln.s, b->fork, 0));
+    int rc = enqueue_frame(b->dptrs, ln.groups, ln.count, b->n_k, 1, ln.s, NoTiming{});
+    if (rc != DDH_OK) return rc;
+    DDH_CHECK(hipEventRecord(ln.join, ln.s));
+  }
+  for (Lane& ln : b->lanes) DDH_CHECK(hipStreamWaitEvent(st, ln.join, 0));
+  return DDH_OK;
+}
+
 int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
   if (!b || !y) return DDH_EINVAL;
   if (!b->alive()) return DDH_ESTATE;
@@ -693,14 +770,18 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
     b->recs.push_back({kind, a, c});
     return e;
   };
-  hipError_t e = timed(KK_SETY, [&] { return launch_set_y(b->dptrs, b->yord.data(), b->total, st); });
-  if (e != hipSuccess) return hip_fail(e, "launch_set_y");
+  hipError_t e = timed(KK_BEGIN, [&] { return launch_begin(b->dptrs, b->yord.data(), b->total, b->n_k, st); });
+  if (e != hipSuccess) return hip_fail(e, "launch_begin");
   const bool graph = (b->flags & DDH_BATCH_GRAPH) && !b->timing;
-  if (graph) {
+  if (b->timing) {
+    // per-kernel timing: every lane's launches in sequence on the caller's stream
+    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed);
+    if (rc != DDH_OK) return rc;
+  } else if (graph) {
     if (!b->gexec) {
       hipGraph_t g = nullptr;
       DDH_CHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-      int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, b->cap, NoTiming{});
+      int rc = enqueue_lanes(b, b->cap);
       hipError_t ec = hipStreamEndCapture(b->cap, &g);
       if (rc != DDH_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -716,7 +797,7 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
     }
     DDH_CHECK(hipGraphLaunch(b->gexec, st));
   } else {
-    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed);
+    int rc = enqueue_lanes(b, st);
     if (rc != DDH_OK) return rc;
   }
   for (ddh_stream_t s : b->streams) {
@@ -731,13 +812,126 @@ int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const cha
   if (!b->alive()) return DDH_ESTATE;
   int rc = drain_timing(b);
   if (rc != DDH_OK) return rc;
-  const int m = std::min(*n, (int)KK_COUNT + 1);
+  const int m = std::min(*n, (int)KK_COUNT);
   for (int k = 0; k < m; ++k) {
     if (ms) ms[k] = b->acc_ms[k];
     if (calls) calls[k] = b->acc_n[k];
     if (names) names[k] = kKindNames[k];
   }
   *n = m;
+  return DDH_OK;
+}
+
+// ------------------------------------------------------------------- tiles
+int ddh_set_tiles(int N, const int* cfg) {
+  if (!valid_N(N) || !cfg) return DDH_EINVAL;
+  TileConfig t{cfg[0], cfg[1], cfg[2], cfg[3]};
+  if (!tiles_ok(N, t)) return DDH_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  tile_cache()[N] = t;
+  return DDH_OK;
+}
+
+int ddh_get_tiles(int N, int* cfg) {
+  if (!valid_N(N) || !cfg) return DDH_EINVAL;
+  TileConfig t = tiles_for(N);
+  cfg[0] = t.row_lines;
+  cfg[1] = t.col_width;
+  cfg[2] = t.m_tile_h;
+  cfg[3] = t.m_tile_w;
+  return DDH_OK;
+}
+
+int ddh_autotune(int N, int count, int* cfg, double* us) {
+  if (!valid_N(N) || count < 1 || count > 4096) return DDH_EINVAL;
+  const int rows_c[4] = {4, 8, 16, 32}, cols_c[4] = {4, 8, 16, 32};
+  const int ms_c[8][2] = {{16, 16}, {16, 32}, {16, 64}, {32, 32}, {32, 64}, {64, 64}, {32, 128}, {0, 0}};
+  std::vector<int> rows, cols;
+  std::vector<std::pair<int, int>> mss;
+  const TileConfig base = tiles_for(N);
+  for (int v : rows_c)
+    if (tiles_ok(N, {v, base.col_width, base.m_tile_h, base.m_tile_w})) rows.push_back(v);
+  for (int v : cols_c)
+    if (tiles_ok(N, {base.row_lines, v, base.m_tile_h, base.m_tile_w})) cols.push_back(v);
+  for (auto& m : ms_c)
+    if (tiles_ok(N, {base.row_lines, base.col_width, m[0], m[1]})) mss.push_back({m[0], m[1]});
+  if (rows.empty() || cols.empty() || mss.empty()) return DDH_EINVAL;
+  ddh_params p;
+  ddh_default_params(N, &p);
+  std::vector<ddh_stream_t> ss;
+  float2* ybuf = nullptr;
+  int rc = DDH_OK;
+  auto cleanup = [&]() {
+    for (ddh_stream_t s : ss) ddh_destroy_stream(s);
+    if (ybuf) (void)hipFree(ybuf);
+  };
+  const size_t px = (size_t)N * N;
+  hipError_t e = hipMalloc(&ybuf, sizeof(float2) * px * count);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(autotune)");
+  e = launch_synth_frames(ybuf, (long long)(px * count), 12345u, nullptr);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "synth_frames");
+  }
+  for (int i = 0; i < count && rc == DDH_OK; ++i) {
+    ddh_stream_t s = nullptr;
+    rc = ddh_init_stream(&p, nullptr, &s);
+    if (rc == DDH_OK) ss.push_back(s);
+  }
+  if (rc != DDH_OK) {
+    cleanup();
+    return rc;
+  }
+  std::vector<const void*> ys(count);
+  for (int i = 0; i < count; ++i) ys[i] = ybuf + px * i;
+  const int ncand = (int)std::max({rows.size(), cols.size(), mss.size()});
+  std::vector<double> t_rows(rows.size(), 1e30), t_cols(cols.size(), 1e30), t_ms(mss.size(), 1e30);
+  for (int c = 0; c < ncand && rc == DDH_OK; ++c) {
+    const int ir = std::min(c, (int)rows.size() - 1), ic = std::min(c, (int)cols.size() - 1),
+              im = std::min(c, (int)mss.size() - 1);
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      tile_cache()[N] = TileConfig{rows[ir], cols[ic], mss[im].first, mss[im].second};
+    }
+    ddh_batch_t b = nullptr;
+    rc = ddh_batch_create(ss.data(), count, 0, &b);
+    if (rc != DDH_OK) break;
+    for (int f = 0; f < 2 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), nullptr);
+    if (rc == DDH_OK) rc = ddh_batch_set_timing(b, 1);
+    for (int f = 0; f < 5 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), nullptr);
+    double ms[KK_COUNT];
+    long long calls[KK_COUNT];
+    int n = KK_COUNT;
+    if (rc == DDH_OK) rc = ddh_batch_stage_times(b, ms, calls, nullptr, &n);
+    ddh_batch_destroy(b);
+    if (rc != DDH_OK) break;
+    auto avg = [&](int kk) { return calls[kk] ? 1e3 * ms[kk] / calls[kk] : 1e30; };
+    t_rows[ir] = std::min(t_rows[ir], avg(KK_ROW1) + avg(KK_ROW2));
+    t_cols[ic] = std::min(t_cols[ic], avg(KK_COL));
+    t_ms[im] = std::min(t_ms[im], avg(KK_MSTEP));
+  }
+  const int br = (int)(std::min_element(t_rows.begin(), t_rows.end()) - t_rows.begin());
+  const int bc = (int)(std::min_element(t_cols.begin(), t_cols.end()) - t_cols.begin());
+  const int bm = (int)(std::min_element(t_ms.begin(), t_ms.end()) - t_ms.begin());
+  const TileConfig best{rows[br], cols[bc], mss[bm].first, mss[bm].second};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    tile_cache()[N] = rc == DDH_OK ? best : base;
+  }
+  cleanup();
+  if (rc != DDH_OK) return rc;
+  if (cfg) {
+    cfg[0] = best.row_lines;
+    cfg[1] = best.col_width;
+    cfg[2] = best.m_tile_h;
+    cfg[3] = best.m_tile_w;
+  }
+  if (us) {
+    us[0] = t_rows[br];  // row-ifft + row-fft
+    us[1] = t_cols[bc];
+    us[2] = 0.0;
+    us[3] = t_ms[bm];
+  }
   return DDH_OK;
 }
 

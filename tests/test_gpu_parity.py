@@ -427,3 +427,70 @@ def test_full_size_batch_sampled_against_oracle():
             orc[i] = O.ddh_frame(*orc[i], sims[i].frame(n).astype(np.complex128), a, pairs[i][0])
             compare(f"stream {i} frame {n}", *state(streams[i]), *orc[i], a)
     b.close()
+
+
+# ----------------------------------------------------------------------------- tiling
+
+def _run_frames(D, N, gp, frames):
+    s = D.Stream(N, gp)
+    for y in frames:
+        s.step(y)
+    return state(s)
+
+
+@pytest.mark.parametrize("N", [64, 256, 512])
+def test_tilings_give_bitwise_identical_results(N):
+    D = _ddh()
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=10.0, snr=6.0, config_id=18))
+    _, gp = make_pair(N, st.sigma_w2)
+    frames = [dev(st.frame(n)) for n in range(3)]
+    saved = D.get_tiles(N)
+    cfgs = [(4, 4, 16, 16), (8, 32, 16, 64), (32, 8, 32, 32), (16, 16, 32, 64), (4, 8, 64, 64), (8, 8, 32, 128),
+            (16, 16, 0, 0)]
+    ref = None
+    try:
+        for cfg in cfgs:
+            if cfg[2] > N or cfg[3] > N:
+                continue
+            say(f"tiles N={N} cfg={cfg}")
+            D.set_tiles(N, cfg)
+            out = _run_frames(D, N, gp, frames)
+            if ref is None:
+                ref = out
+            else:
+                np.testing.assert_array_equal(out[0], ref[0])
+                np.testing.assert_array_equal(out[1], ref[1])
+    finally:
+        D.set_tiles(N, saved)
+
+
+def test_autotune_installs_a_valid_tiling():
+    D = _ddh()
+    N = 128
+    cfg, us = D.autotune(N, 8)
+    say(f"  autotune N={N}: cfg={cfg} us={us}")
+    assert D.get_tiles(N) == cfg
+    assert all(u > 0 for u in (us[0], us[1], us[3]))
+    with pytest.raises(D.DDHError):
+        D.set_tiles(N, (3, 8, 16, 16))
+
+
+@pytest.mark.parametrize("lanes,graph", [(2, False), (3, True), (4, True)])
+def test_batch_lanes_equal_single_lane(lanes, graph):
+    D = _ddh()
+    specs = _mixed_specs()
+    sims = [synth.Stream(sp) for sp in specs]
+    pairs = [make_pair(sp.N, sm.sigma_w2) for sp, sm in zip(specs, sims)]
+    frames = [[dev(sm.frame(n)) for n in range(3)] for sm in sims]
+    res = []
+    for nl in (1, lanes):
+        say(f"lanes={nl} graph={graph}")
+        streams = [D.Stream(sp.N, pairs[i][1]) for i, sp in enumerate(specs)]
+        b = D.Batch(streams, graph=graph, lanes=nl)
+        for n in range(3):
+            b.step([frames[i][n] for i in range(len(specs))])
+        res.append([state(s) for s in streams])
+        b.close()
+    for (r0, p0), (r1, p1) in zip(*res):
+        np.testing.assert_array_equal(r0, r1)
+        np.testing.assert_array_equal(p0, p1)
