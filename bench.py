@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=60)
     p.add_argument("--no-extras", action="store_true", help="only the timed batched step (for profiling)")
-    p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--autotune", action="store_true", help="time every tiling first and keep the fastest")
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     return p.parse_args()
 
@@ -76,6 +76,22 @@ def kernel_bytes(N, fill):
         "row_fft": 8 + 12 * f + 8 * f,          # U; y, phi on the pupil; (kappa, theta~) on the pupil
         "m_step": 4 + 4 + 12 * f + 4 + 4 * f,   # r, |b|^2, phi, (kappa, theta~); r, phi (pupil)
     }
+
+
+def recorded_traffic(kernel_kind, tiles):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (profiles/m_step_traffic.json), or None when the kernel source or
+    the tiling has changed since the counters were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "m_step_traffic.json")
+    src = os.path.join(ROOT, "paper_2305_03284_amd", "csrc", "ddh_kernels.hip")
+    if kernel_kind != "m_step" or not os.path.exists(rec_path):
+        return None
+    rec = json.load(open(rec_path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha256_prefix") != sha or list(rec.get("tiles", [])) != list(tiles):
+        return None
+    return int(rec["traffic_bytes"])
 
 
 def oracle_baseline(specs, frames, n_frames_cpu):
@@ -133,7 +149,7 @@ def main():
     for n_ in sorted({sp.N for sp in specs}):
         if args.tiles:
             D.set_tiles(n_, [int(v) for v in args.tiles.split(",")])
-        elif not args.no_autotune:
+        elif args.autotune:
             D.autotune(n_, sum(1 for sp in specs if sp.N == n_))
         tiles[n_] = D.get_tiles(n_)
 
@@ -214,7 +230,7 @@ def main():
         if "GB_s" in kernels[dom]:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"], "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
-                               "traffic": None}
+                               "traffic": recorded_traffic(dom, tiles.get(args.N, ()))}
         step_bytes_floor = 56 * px_total  # compulsory + one global round trip per 2-D FFT
         step_bytes_alg = sum(kb[k] for k in kb) * px_total
         out["kernels"] = kernels

@@ -755,7 +755,9 @@ struct MsGeom {
   static constexpr int nu(int c) { return (RH - c - 1 - li0(c) + 1) / 2; }
   static constexpr int nv(int c) { return (RW - c - 1 - lj0(c) + 1) / 2; }
   static constexpr int n(int c) { return nu(c) * nv(c); }
-  static constexpr int rounds(int c) { return (n(c) + MS_THREADS - 1) / MS_THREADS; }
+  // block size: one round per pass when the first (largest) pass fits in 1024 threads
+  static constexpr int BT = ((n(0) + 63) / 64) * 64 <= 1024 ? ((n(0) + 63) / 64) * 64 : MS_THREADS;
+  static constexpr int rounds(int c) { return (n(c) + BT - 1) / BT; }
   static constexpr int slot0(int c) { return c == 0 ? 0 : slot0(c - 1) + rounds(c - 1); }
   static constexpr int SLOTS = rounds(0) + rounds(1) + rounds(2) + rounds(3);
   static __device__ __forceinline__ int offset(int c, int idx) {
@@ -799,8 +801,10 @@ __device__ __forceinline__ float phi_update(const float* sP, int o, float P, flo
 // (shared L2 for the halo).
 // ---------------------------------------------------------------------------
 template <int N, int TH, int TW>
-__global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane, int do_rinit) {
+__global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane,
+                                                              int do_rinit) {
   using G = MsGeom<TH, TW>;
+  constexpr int BT = G::BT;
   constexpr int RW = G::RW, RP = G::RP, SLOTS = G::SLOTS;
   constexpr int TPC = N / TW, TPR = N / TH;
   constexpr int TILES = TPC * TPR;
@@ -828,7 +832,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, 
 #define DDH_OWN(C)                                                           \
   _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {             \
     const int slot = G::slot0(C) + rd;                                       \
-    const int idx = threadIdx.x + rd * MS_THREADS;                           \
+    const int idx = threadIdx.x + rd * BT;                           \
     ob[slot] = 0.f;                                                          \
     orp[slot] = 0.f;                                                         \
     okap[slot] = 0.f;                                                        \
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, 
   DDH_OWN(0) DDH_OWN(1) DDH_OWN(2) DDH_OWN(3)
 #undef DDH_OWN
   if (sc[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
-    for (int idx = threadIdx.x; idx < TH * TW; idx += MS_THREADS) {
+    for (int idx = threadIdx.x; idx < TH * TW; idx += BT) {
       const int gi = ti * TH + idx / TW, gj = tj * TW + idx % TW;
       rout[gi * N + gj] = rin[gi * N + gj];
       pout[gi * N + gj] = pin[gi * N + gj];
@@ -864,7 +868,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, 
   }
   const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
   // ---- stage the region: r after the Eq. (3) initialisation, phi' and flags
-  for (int idx = threadIdx.x; idx < RP; idx += MS_THREADS) {
+  for (int idx = threadIdx.x; idx < RP; idx += BT) {
     const int li = idx / RW, lj = idx - li * RW;
     const int gi = gi0 + li, gj = gj0 + lj;
     float r = 0.f, p = 0.f;
@@ -920,7 +924,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_mstep(StreamDesc* const* dptrs, 
   __syncthreads();
   DDH_PASS(0) DDH_PASS(1) DDH_PASS(2) DDH_PASS(3)
 #undef DDH_PASS
-  for (int idx = threadIdx.x; idx < TH * TW; idx += MS_THREADS) {
+  for (int idx = threadIdx.x; idx < TH * TW; idx += BT) {
     const int li = 4 + idx / TW, lj = 4 + idx % TW;
     const int o = li * RW + lj;
     const int gi = gi0 + li, gj = gj0 + lj;
@@ -1338,7 +1342,8 @@ static hipError_t mstep_n(StreamDesc* const* d, int count, int k, int use_plane,
 #define DDH_M(TH, TW)                                                                                          \
   if (th == TH && tw == TW) {                                                                                  \
     if constexpr (N % TH == 0 && N % TW == 0) {                                                                \
-      hipLaunchKernelGGL((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3(MS_THREADS), 0, st, d, k, \
+      hipLaunchKernelGGL((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3((MsGeom<TH, TW>::BT)), 0, st, \
+                         d, k,                                                                                 \
                          use_plane, do_rinit);                                                                 \
       return hipGetLastError();                                                                                \
     }                                                                                                          \

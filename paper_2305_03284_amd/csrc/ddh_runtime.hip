@@ -85,10 +85,10 @@ int ensure_twiddles(int dev, float2** out) {
 
 TileConfig default_tiles(int N) {
   switch (N) {
-    case 64: return {32, 32, 32, 64};
-    case 128: return {32, 32, 32, 64};
-    case 256: return {16, 16, 32, 64};
-    default: return {8, 8, 32, 64};
+    case 64: return {32, 32, 32, 32};
+    case 128: return {16, 16, 32, 32};
+    case 256: return {16, 16, 32, 32};
+    default: return {8, 8, 32, 32};
   }
 }
 
