@@ -243,15 +243,40 @@ __device__ __forceinline__ int last_pos(int i, int t) {
 }
 
 // ---------------------------------------------------------------------------
+// Global-memory views.  The descriptors hold generic pointers; memory reached
+// through a generic pointer is accessed with flat instructions, which also
+// count against the LDS/scalar wait counter, so every LDS wait would stall
+// behind outstanding HBM loads.  All these buffers live in global memory: the
+// kernels read their descriptor and the buffers through address-space-1
+// views.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;  // the host pass only parses kernel bodies
+#endif
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ auto& desc_ref(T* p) {
+  return *glb(p);
+}
+
+// ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool in_pupil(int i, int j, int N, float d2) {
   const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
   return (float)(di * di + dj * dj) <= d2;
 }
-__device__ __forceinline__ float plane_at(const float* sc, int i, int j, int N) {
+// least-squares plane c0 + c1 (i - c) + c2 (j - c), c = (N-1)/2 (RemoveTipTilt)
+__device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, int j, int N) {
   const float cc = 0.5f * (float)(N - 1);
-  return __builtin_fmaf(sc[SC_C2], (float)j - cc, __builtin_fmaf(sc[SC_C1], (float)i - cc, sc[SC_C0]));
+  return __builtin_fmaf(c2, (float)j - cc, __builtin_fmaf(c1, (float)i - cc, c0));
 }
 
 // Eq. (3) initialisation and E-step statistics, shared by k_col and k_mstep so
@@ -301,7 +326,7 @@ struct YArgs {
 __global__ void k_begin(StreamDesc* const* dptrs, YArgs a, int count, int iters) {
   const int i = threadIdx.x;
   if (i < count) {
-    StreamDesc* d = dptrs[i];
+    const auto d = glb(dptrs[i]);
     d->y = a.p[i];
     d->cur = (d->cur + d->pending) & 1;
     d->pending = iters;
@@ -315,16 +340,16 @@ __global__ void k_begin(StreamDesc* const* dptrs, YArgs a, int count, int iters)
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int with_phi) {
-  const StreamDesc& D = *dptrs[blockIdx.y];
+  const auto& D = desc_ref(dptrs[blockIdx.y]);
   __shared__ float red[6 * 16];
   const int base = blockIdx.x * STATS_PIX_PER_BLOCK;
   constexpr float c = 0.5f * (float)(N - 1);
   float2 v[16];
   float ph[16];
-  const float* phi = D.phi[D.cur];
+  const float* phi = glb(D.phi[D.cur]);
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = D.y[base + k * 256 + threadIdx.x];
+  for (int k = 0; k < 16; ++k) v[k] = glb(D.y)[base + k * 256 + threadIdx.x];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int idx = base + k * 256 + threadIdx.x;
@@ -359,7 +384,7 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int wit
     block_sum<3>(ps, red);
   }
   if (threadIdx.x == 0) {
-    float* out = D.part + blockIdx.x * PART_STRIDE;
+    float* out = glb(D.part) + blockIdx.x * PART_STRIDE;
     out[0] = mr;
     out[1] = mi;
     out[2] = m2[0];
@@ -379,14 +404,15 @@ __device__ __forceinline__ double wave_sum_d(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
-__device__ void combine_stats(const StreamDesc& D, int with_phi, float* out) {
+template <class Desc>
+__device__ void combine_stats(const Desc& D, int with_phi, float* out) {
   const int lane = threadIdx.x & 63;
   const int N = D.N;
   const int nb = (N * N) / STATS_PIX_PER_BLOCK;
   double p[6] = {0, 0, 0, 0, 0, 0};
   if (lane < nb) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) p[q] = D.part[lane * PART_STRIDE + q];
+    for (int q = 0; q < 6; ++q) p[q] = glb(D.part)[lane * PART_STRIDE + q];
   }
   const double mr = wave_sum_d(p[0]) / nb, mi = wave_sum_d(p[1]) / nb;
   const double dr = lane < nb ? p[0] - mr : 0.0, di = lane < nb ? p[1] - mi : 0.0;
@@ -417,8 +443,8 @@ __device__ void combine_stats(const StreamDesc& D, int with_phi, float* out) {
 
 // k_finalize: standalone combine (diagnostic path).  grid (streams), block 64
 __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int with_phi) {
-  const StreamDesc& D = *dptrs[blockIdx.x];
-  combine_stats(D, with_phi, D.scal);
+  const auto& D = desc_ref(dptrs[blockIdx.x]);
+  combine_stats(D, with_phi, glb(D.scal));
 }
 
 // ---------------------------------------------------------------------------
@@ -433,11 +459,11 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
   __shared__ float2 s_tw[N];
   __shared__ float scs[SC_COUNT];
-  const StreamDesc& D = *dptrs[blockIdx.y];
+  const auto& D = desc_ref(dptrs[blockIdx.y]);
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
   const int row = blockIdx.x * LPW + line;
-  const float* phi = D.phi[(D.cur + k) & 1] + row * N;
-  const float2* y = D.y + row * N;
+  const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
+  const float2* y = glb(D.y) + row * N;
   // global reads first (they depend on nothing computed here): the row of y
   // and phi, and the twiddle table into LDS
   float2 yv[E];
@@ -449,24 +475,29 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
     phv[i] = phi[n];
   }
   for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
-  const float* sc = D.scal;
+  float sc[SC_COUNT];
   if (fin) {
     // first EM iteration of a frame: every block combines the stats partials
     // itself (identical arithmetic in all blocks); block 0 publishes them
     if (threadIdx.x < 64) combine_stats(D, with_phi, scs);
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) D.scal[threadIdx.x] = scs[threadIdx.x];
-    sc = scs;
+    if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) glb(D.scal)[threadIdx.x] = scs[threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < SC_COUNT; ++q) sc[q] = scs[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < SC_COUNT; ++q) sc[q] = glb(D.scal)[q];
   }
   if (sc[SC_FLAG] != 0.0f) return;
   const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
   const float scale = sc[SC_SCALE];
+  const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
   float2 v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
     if (in_pupil(row, n, N, D.pupil_d2)) {
-      const float p = use_plane ? phv[i] - plane_at(sc, row, n, N) : phv[i];
+      const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, n, N) : phv[i];
       float sn, cs;
       fsincos(p, &sn, &cs);
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
@@ -477,7 +508,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   }
   RowLds<N> L{lds + line * RowLds<N>::STRIDE};
   line_fft<N, +1>(v, t, L, s_tw);
-  float2* out = D.T + row * N;
+  float2* out = glb(D.T) + row * N;
 #pragma unroll
   for (int i = 0; i < E; ++i) out[last_pos<N, +1>(i, t)] = v[i];
 }
@@ -495,20 +526,20 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
   constexpr int E = Plan<N>::E;
   __shared__ float2 lds[N * ColLds<W>::STRIDE];
   __shared__ float2 s_tw[N];
-  const StreamDesc& D = *dptrs[blockIdx.y];
+  const auto& D = desc_ref(dptrs[blockIdx.y]);
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int col = blockIdx.x * W + w;
   float2 v[E];
   float rpv[E];
-  const float* rin = D.r[(D.cur + k) & 1];
-  float* rmat = D.r[((D.cur + k) & 1) ^ 1];
+  const float* rin = glb(D.r[(D.cur + k) & 1]);
+  float* rmat = glb(D.r[((D.cur + k) & 1) ^ 1]);
   // global reads first: the column, this thread's r values, the twiddles
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = D.T[first_pos<N, +1>(i, t) * N + col];
+  for (int i = 0; i < E; ++i) v[i] = glb(D.T)[first_pos<N, +1>(i, t) * N + col];
 #pragma unroll
   for (int i = 0; i < E; ++i) rpv[i] = rin[last_pos<N, +1>(i, t) * N + col];
   for (int i = threadIdx.x; i < N; i += W * (N / E)) s_tw[i] = tw[i];
-  if (D.scal[SC_FLAG] != 0.0f) return;
+  if (glb(D.scal)[SC_FLAG] != 0.0f) return;
   ColLds<W> L{lds + w};
   line_fft<N, +1>(v, t, L, s_tw);
   const float invN = 1.0f / (float)N;
@@ -521,14 +552,14 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
     const float rp = rpv[i];
     const float ri = do_rinit ? rinit_of(rp, bb, lam, alpha, fl) : rp;
     const float wgt = wiener_of(ri, s2);
-    D.bb[n * N + col] = bb;
+    glb(D.bb)[n * N + col] = bb;
     if (mat) rmat[n * N + col] = ri;  // the colour passes update this copy in place
     v[i] = cscale(b, wgt);
   }
   __syncthreads();
   line_fft<N, -1>(v, t, L, s_tw);
 #pragma unroll
-  for (int i = 0; i < E; ++i) D.U[last_pos<N, -1>(i, t) * N + col] = v[i];
+  for (int i = 0; i < E; ++i) glb(D.U)[last_pos<N, -1>(i, t) * N + col] = v[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -544,15 +575,15 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
   __shared__ float2 s_tw[N];
-  const StreamDesc& D = *dptrs[blockIdx.y];
-  const float* sc = D.scal;
+  const auto& D = desc_ref(dptrs[blockIdx.y]);
+  const float* sc = glb(D.scal);
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
   const int row = blockIdx.x * LPW + line;
   for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
   float2 v[E];
-  const float2* u = D.U + row * N;
-  const float* phi = D.phi[(D.cur + k) & 1] + row * N;
-  const float2* y = D.y + row * N;
+  const float2* u = glb(D.U) + row * N;
+  const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
+  const float2* y = glb(D.y) + row * N;
   // every global read is issued up front: the row, and y and phi at this
   // thread's output positions that lie in the pupil
   float2 yv[E];
@@ -575,9 +606,10 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   const float invN = 1.0f / (float)N;
   const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
   const float scale = sc[SC_SCALE];
+  const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
   const float c2s = 2.0f / D.sigma2;
-  float2* out = D.T + row * N;
-  float* pmat = D.phi[((D.cur + k) & 1) ^ 1] + row * N;
+  float2* out = glb(D.T) + row * N;
+  float* pmat = glb(D.phi[((D.cur + k) & 1) ^ 1]) + row * N;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int m = last_pos<N, -1>(i, t);
@@ -585,7 +617,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
     if (in_pupil(row, m, N, D.pupil_d2)) {
       const float2 z = cscale(v[i], invN);
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
-      const float p = use_plane ? phv[i] - plane_at(sc, row, m, N) : phv[i];
+      const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, m, N) : phv[i];
       // w = exp(j p) conj(yhat) z: |w| = |yhat||z| and arg w = p - theta, so
       // x0 = arg w lies in (-pi, pi] already and c sin(x0) = (2/s2) Im w.
       float sn, cs;
@@ -693,10 +725,6 @@ __device__ __forceinline__ float qg_shape(float d, float inv_Ts, float pmq, floa
 // bit-identical results.  Neighbour order: up, down, left, right, up-left,
 // up-right, down-left, down-right (edges weight 1/6, diagonals 1/12).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, int j, int N) {
-  const float cc = 0.5f * (float)(N - 1);
-  return __builtin_fmaf(c2, (float)j - cc, __builtin_fmaf(c1, (float)i - cc, c0));
-}
 // r update of one pixel from its 8 neighbours (ok[e] = neighbour exists)
 __device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], const bool (&ok)[8], float inv_sp,
                                          float inv_Ts, float pmq, float qop, float fl) {
@@ -793,12 +821,14 @@ __device__ __forceinline__ float phi_update(const float* sP, int o, float P, flo
 // k_mstep: one 4-colour sweep of the r and phi M-steps on a TH x TW output
 // tile.  The tile and a 4-pixel halo of r and phi are staged in LDS; pass c
 // updates the colour-c pixels of the region shrunk by c+1, so the inner tile
-// sees exactly the values a whole-grid sweep produces.  Each thread keeps the
-// per-pixel constants (s, kappa, theta~) of the pixels it updates in
-// registers.  Colour(i, j) = (i mod 2) + 2 (j mod 2).  Reads state buffer
-// in = (cur + k) & 1, writes in ^ 1.  grid (tiles, streams), block 256; blocks
-// are remapped so that neighbouring tiles of a stream run on the same XCD
-// (shared L2 for the halo).
+// sees exactly the values a whole-grid sweep produces.  All global reads of
+// a block are issued before the first wait.  s = E|g|^2 is computed once per
+// staged pixel; each thread keeps the per-pixel constants (s, kappa, theta~)
+// of the pixels it updates in registers.  Colour(i, j) = (i mod 2) +
+// 2 (j mod 2).  Reads state buffer in = (cur + k) & 1, writes in ^ 1.
+// grid (tiles, streams), block BT (the first pass's pixel count rounded up to
+// whole waves); blocks are remapped so that neighbouring tiles of a stream run
+// on the same XCD (shared L2 for the halo).
 // ---------------------------------------------------------------------------
 template <int N, int TH, int TW>
 __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane,
@@ -808,53 +838,66 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* cons
   constexpr int RW = G::RW, RP = G::RP, SLOTS = G::SLOTS;
   constexpr int TPC = N / TW, TPR = N / TH;
   constexpr int TILES = TPC * TPR;
-  __shared__ float sR[RP], sP[RP];
+  __shared__ float sR[RP], sP[RP], sS[RP];
   __shared__ unsigned char sF[RP];
   const int total = TILES * gridDim.y;
   const int L = blockIdx.x + blockIdx.y * TILES;
   const int logical = (total % 8 == 0) ? (L % 8) * (total / 8) + (L / 8) : L;
   const int g = logical / TILES, tile = logical - g * TILES;
-  const StreamDesc& D = *dptrs[g];
+  const auto& D = desc_ref(dptrs[g]);
   const int ti = tile / TPC, tj = tile - ti * TPC;
   const int gi0 = ti * TH - 4, gj0 = tj * TW - 4;
   const int in = (D.cur + k) & 1;
-  const float* rin = D.r[in];
-  const float* pin = D.phi[in];
-  float* rout = D.r[in ^ 1];
-  float* pout = D.phi[in ^ 1];
-  const float* sc = D.scal;
+  const float* rin = glb(D.r[in]);
+  const float* pin = glb(D.phi[in]);
+  float* rout = glb(D.r[in ^ 1]);
+  float* pout = glb(D.phi[in ^ 1]);
+  const float* sc = glb(D.scal);
   const float d2 = D.pupil_d2;
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
-  constexpr float cc = 0.5f * (float)(N - 1);
-  // ---- global reads for the pixels this thread updates, issued first
-  float ob[SLOTS], orp[SLOTS], okap[SLOTS], ott[SLOTS];
+  // ---- every global read is issued up front: r, |b|^2 and phi of the
+  // region (staging rounds), and (kappa, theta~) of the pupil pixels this
+  // thread updates
+  constexpr int SR = (RP + BT - 1) / BT;
+  const float* bbp = glb(D.bb);
+  const float2* ktp = glb(D.T);
+  float gr[SR], gb[SR], gph[SR];
+#pragma unroll
+  for (int q = 0; q < SR; ++q) {
+    const int idx = threadIdx.x + q * BT;
+    const int li = idx / RW, lj = idx - li * RW;
+    const int gi = gi0 + li, gj = gj0 + lj;
+    gr[q] = 0.f;
+    gb[q] = 0.f;
+    gph[q] = 0.f;
+    if (idx < RP && gi >= 0 && gi < N && gj >= 0 && gj < N) {
+      const int pidx = gi * N + gj;
+      gr[q] = rin[pidx];
+      gb[q] = bbp[pidx];
+      if (in_pupil(gi, gj, N, d2)) gph[q] = pin[pidx];
+    }
+  }
+  float okap[SLOTS], ott[SLOTS];
   int oo[SLOTS];
-#define DDH_OWN(C)                                                           \
-  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {             \
-    const int slot = G::slot0(C) + rd;                                       \
-    const int idx = threadIdx.x + rd * BT;                           \
-    ob[slot] = 0.f;                                                          \
-    orp[slot] = 0.f;                                                         \
-    okap[slot] = 0.f;                                                        \
-    ott[slot] = 0.f;                                                         \
-    oo[slot] = -1;                                                           \
-    if (idx < G::n(C)) {                                                     \
-      const int o = G::offset(C, idx);                                       \
-      const int li = o / RW, lj = o - (o / RW) * RW;                         \
-      const int gi = gi0 + li, gj = gj0 + lj;                                \
-      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {                          \
-        oo[slot] = o;                                                        \
-        const int pidx = gi * N + gj;                                        \
-        orp[slot] = rin[pidx];                                               \
-        ob[slot] = D.bb[pidx];                                               \
-        const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;                  \
-        if ((float)(di * di + dj * dj) <= d2) {                              \
-          const float2 kt = D.T[pidx];                                       \
-          okap[slot] = kt.x;                                                 \
-          ott[slot] = kt.y;                                                  \
-        }                                                                    \
-      }                                                                      \
-    }                                                                        \
+#define DDH_OWN(C)                                                 \
+  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {   \
+    const int slot = G::slot0(C) + rd;                             \
+    const int idx = threadIdx.x + rd * BT;                         \
+    okap[slot] = 0.f;                                              \
+    ott[slot] = 0.f;                                               \
+    oo[slot] = -1;                                                 \
+    if (idx < G::n(C)) {                                           \
+      const int o = G::offset(C, idx);                             \
+      const int gi = gi0 + o / RW, gj = gj0 + (o - (o / RW) * RW); \
+      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {                \
+        oo[slot] = o;                                              \
+        if (in_pupil(gi, gj, N, d2)) {                             \
+          const float2 kt = ktp[gi * N + gj];                      \
+          okap[slot] = kt.x;                                       \
+          ott[slot] = kt.y;                                        \
+        }                                                          \
+      }                                                            \
+    }                                                              \
   }
   DDH_OWN(0) DDH_OWN(1) DDH_OWN(2) DDH_OWN(3)
 #undef DDH_OWN
@@ -867,40 +910,40 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* cons
     return;
   }
   const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
-  // ---- stage the region: r after the Eq. (3) initialisation, phi' and flags
-  for (int idx = threadIdx.x; idx < RP; idx += BT) {
-    const int li = idx / RW, lj = idx - li * RW;
-    const int gi = gi0 + li, gj = gj0 + lj;
-    float r = 0.f, p = 0.f;
-    unsigned char f = 0;
-    if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
-      f = F_GRID;
-      if (gi >= 1 && gi <= N - 2 && gj >= 1 && gj <= N - 2) f |= F_INNER;
-      const int pidx = gi * N + gj;
-      const float rp = rin[pidx];
-      r = do_rinit ? rinit_of(rp, D.bb[pidx], lam, alpha, fl) : rp;
-      const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
-      if ((float)(di * di + dj * dj) <= d2) {
-        f |= F_PUPIL;
-        // the farthest diagonal neighbour inside the disk => all 8 are
-        const int ai = abs(di) + 2, aj = abs(dj) + 2;
-        if ((float)(ai * ai + aj * aj) <= d2) f |= F_PFULL;
-        const float ph = pin[pidx];
-        p = use_plane ? ph - plane_val(c0, c1, c2, gi, gj, N) : ph;
-      }
-    }
-    sR[idx] = r;
-    sP[idx] = p;
-    sF[idx] = f;
-  }
-  // ---- s = E|g|^2 of the own pixels (same arithmetic as the staged r)
-  float os[SLOTS];
+  // ---- stage the region: r after the Eq. (3) initialisation, s = E|g|^2,
+  // phi' and flags
 #pragma unroll
-  for (int slot = 0; slot < SLOTS; ++slot) {
-    const float ri = do_rinit ? rinit_of(orp[slot], ob[slot], lam, alpha, fl) : orp[slot];
-    os[slot] = second_moment(wiener_of(ri, s2), ob[slot], s2);
+  for (int q = 0; q < SR; ++q) {
+    const int idx = threadIdx.x + q * BT;
+    if (idx < RP) {
+      const int li = idx / RW, lj = idx - li * RW;
+      const int gi = gi0 + li, gj = gj0 + lj;
+      float r = 0.f, sv = 0.f, p = 0.f;
+      unsigned char f = 0;
+      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
+        f = F_GRID;
+        if (gi >= 1 && gi <= N - 2 && gj >= 1 && gj <= N - 2) f |= F_INNER;
+        r = do_rinit ? rinit_of(gr[q], gb[q], lam, alpha, fl) : gr[q];
+        sv = second_moment(wiener_of(r, s2), gb[q], s2);
+        const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
+        if ((float)(di * di + dj * dj) <= d2) {
+          f |= F_PUPIL;
+          // the farthest diagonal neighbour inside the disk => all 8 are
+          const int ai = abs(di) + 2, aj = abs(dj) + 2;
+          if ((float)(ai * ai + aj * aj) <= d2) f |= F_PFULL;
+          p = use_plane ? gph[q] - plane_val(c0, c1, c2, gi, gj, N) : gph[q];
+        }
+      }
+      sR[idx] = r;
+      sS[idx] = sv;
+      sP[idx] = p;
+      sF[idx] = f;
+    }
   }
   __syncthreads();
+  float os[SLOTS];
+#pragma unroll
+  for (int slot = 0; slot < SLOTS; ++slot) os[slot] = oo[slot] >= 0 ? sS[oo[slot]] : 0.f;
   const float inv_sp = D.qg_inv_sp, inv_Ts = D.qg_inv_Ts, pmq = D.qg_pmq, qop = D.qg_qop;
   // ---- the four colour passes (same-colour pixels are never neighbours, so
   // each pass updates its pixels in place)
@@ -943,19 +986,19 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* cons
 // ---------------------------------------------------------------------------
 template <int N, int C>
 __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) {
-  const StreamDesc& D = *dptrs[blockIdx.y];
+  const auto& D = desc_ref(dptrs[blockIdx.y]);
   constexpr int H = N / 2;
   const int q = blockIdx.x * 256 + threadIdx.x;  // < N*N/4
   const int u = q / H, v = q - (q / H) * H;
   const int gi = 2 * u + (C & 1), gj = 2 * v + (C >> 1);
   const int p = gi * N + gj;
   const int in = (D.cur + k) & 1;
-  float* rw = D.r[in ^ 1];
-  float* pw = D.phi[in ^ 1];
+  float* rw = glb(D.r[in ^ 1]);
+  float* pw = glb(D.phi[in ^ 1]);
   const bool up = gi > 0, dn = gi < N - 1, lf = gj > 0, rt = gj < N - 1;
   // global reads first
   const float rp = rw[p];
-  const float bb = D.bb[p];
+  const float bb = glb(D.bb)[p];
   float rq[8];
   rq[0] = up ? rw[p - N] : 0.f;
   rq[1] = dn ? rw[p + N] : 0.f;
@@ -980,11 +1023,11 @@ __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) 
     pq[5] = (up && rt) ? pw[p - N + 1] : 0.f;
     pq[6] = (dn && lf) ? pw[p + N - 1] : 0.f;
     pq[7] = (dn && rt) ? pw[p + N + 1] : 0.f;
-    kt = D.T[p];
+    kt = glb(D.T)[p];
   }
-  if (D.scal[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
-    rw[p] = D.r[in][p];
-    pw[p] = D.phi[in][p];
+  if (glb(D.scal)[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
+    rw[p] = glb(D.r[in])[p];
+    pw[p] = glb(D.phi[in])[p];
     return;
   }
   // ---- r update
@@ -1039,7 +1082,8 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col_plain(const float2* 
 // ---------------------------------------------------------------------------
 // Diagnostics (FP64 reductions)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double qg_rho_d(double d, const StreamDesc& D) {
+template <class Desc>
+__device__ __forceinline__ double qg_rho_d(double d, const Desc& D) {
   const double ad = fabs(d);
   const double p = D.qg_p, q = D.qg_q, T = D.qg_T, sg = D.qg_sigma;
   return pow(ad, p) / (p * pow(sg, p)) / (1.0 + pow(ad / (T * sg), p - q));
@@ -1069,11 +1113,11 @@ __device__ __forceinline__ void block_sum_d(double (&x)[NV], double* red) {
 
 // per-pixel terms of the monitored cost; b = A_phi^H yhat for the current phi.
 __global__ __launch_bounds__(256) void k_cost_terms(const StreamDesc* dp, int parity, const float2* b, double* partials) {
-  const StreamDesc& D = *dp;
+  const auto& D = desc_ref(dp);
   __shared__ double red[16];
   const int N = D.N;
-  const float* r = D.r[parity];
-  const float* phi = D.phi[parity];
+  const float* r = glb(D.r[parity]);
+  const float* phi = glb(D.phi[parity]);
   const double s2 = D.sigma2;
   double acc[1] = {0.0};
   const int total = N * N;
@@ -1103,10 +1147,10 @@ __global__ __launch_bounds__(256) void k_cost_terms(const StreamDesc* dp, int pa
 // psi = phi - phi_true on the pupil: plane-fit sums (FP64 partials).
 __global__ __launch_bounds__(256) void k_strehl_sums(const StreamDesc* dp, int parity, const float* phi_true,
                                                      double* partials) {
-  const StreamDesc& D = *dp;
+  const auto& D = desc_ref(dp);
   __shared__ double red[3 * 16];
   const int N = D.N;
-  const float* phi = D.phi[parity];
+  const float* phi = glb(D.phi[parity]);
   const double c = 0.5 * (N - 1);
   double acc[3] = {0, 0, 0};
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
@@ -1128,9 +1172,9 @@ __global__ __launch_bounds__(256) void k_strehl_sums(const StreamDesc* dp, int p
 // field = a exp(j (psi - plane)); with phi_true == nullptr the field is a itself.
 __global__ __launch_bounds__(256) void k_strehl_field(const StreamDesc* dp, int parity, const float* phi_true,
                                                       const double* coef, float2* field) {
-  const StreamDesc& D = *dp;
+  const auto& D = desc_ref(dp);
   const int N = D.N;
-  const float* phi = D.phi[parity];
+  const float* phi = glb(D.phi[parity]);
   const double c = 0.5 * (N - 1);
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
     const int i = idx / N, j = idx - i * N;
@@ -1178,14 +1222,14 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1_cur(const StreamD
                                                                  const float2* __restrict__ tw, float2* work) {
   constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
-  const StreamDesc& D = *dp;
-  const float* sc = D.scal;
+  const auto& D = desc_ref(dp);
+  const float* sc = glb(D.scal);
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
   const int row = blockIdx.x * LPW + line;
   const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
   const float scale = sc[SC_SCALE];
-  const float* phi = D.phi[parity] + row * N;
-  const float2* y = D.y + row * N;
+  const float* phi = glb(D.phi[parity]) + row * N;
+  const float2* y = glb(D.y) + row * N;
   float2 v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
