@@ -14,6 +14,7 @@
 #include "ddh_internal.h"
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 namespace ddh {
 
@@ -267,14 +268,25 @@ __device__ __forceinline__ auto& desc_ref(T* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Arithmetic that more than one kernel evaluates for the same pixel (Eq. (3),
+// the E-step statistics, the M-step pixel updates) is written with explicit
+// FMAs and compiled without contraction, so every kernel and every tiling
+// rounds it identically.
+// ---------------------------------------------------------------------------
+#define DDH_EXACT_FP _Pragma("clang fp contract(off)")
+
+// ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
+// (|2i - N + 1| < 2^23: the squares use the full-rate 24-bit multiplier)
 __device__ __forceinline__ bool in_pupil(int i, int j, int N, float d2) {
   const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
-  return (float)(di * di + dj * dj) <= d2;
+  return (float)(__mul24(di, di) + __mul24(dj, dj)) <= d2;
 }
+
 // least-squares plane c0 + c1 (i - c) + c2 (j - c), c = (N-1)/2 (RemoveTipTilt)
 __device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, int j, int N) {
+  DDH_EXACT_FP
   const float cc = 0.5f * (float)(N - 1);
   return __builtin_fmaf(c2, (float)j - cc, __builtin_fmaf(c1, (float)i - cc, c0));
 }
@@ -282,10 +294,15 @@ __device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, 
 // Eq. (3) initialisation and E-step statistics, shared by k_col and k_mstep so
 // that both evaluate exactly the same FP32 operations.
 __device__ __forceinline__ float rinit_of(float rp, float bb, float lam, float alpha, float floor_) {
+  DDH_EXACT_FP
   return fmaxf(__builtin_fmaf(1.0f - lam, rp, (lam * alpha) * bb), floor_);
 }
-__device__ __forceinline__ float wiener_of(float r, float s2) { return r * __builtin_amdgcn_rcpf(r + s2); }
+__device__ __forceinline__ float wiener_of(float r, float s2) {
+  DDH_EXACT_FP
+  return r * __builtin_amdgcn_rcpf(r + s2);
+}
 __device__ __forceinline__ float second_moment(float w, float bb, float s2) {
+  DDH_EXACT_FP
   // s = C + |mu|^2 = s2 w + w^2 |b|^2
   return __builtin_fmaf(s2, w, (w * w) * bb);
 }
@@ -645,6 +662,7 @@ __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(
 __device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fcbrt(float x) {  // real cube root
+  DDH_EXACT_FP
   const float m = fexp2(flog2(fabsf(x)) * (1.0f / 3.0f));
   return copysignf(m, x);
 }
@@ -660,9 +678,11 @@ __device__ __forceinline__ float fcos_rev(float rev) { return __builtin_amdgcn_c
 // h(rho1) - h(rho3) written as one difference; ties take the smaller root.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float cubic_f(float A, float B, float s, float x) {
+  DDH_EXACT_FP
   return __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A, x, -B), x, 1.0f), x, -s);
 }
 __device__ __forceinline__ float polish(float A, float B, float s, float x) {
+  DDH_EXACT_FP
   float f = cubic_f(A, B, s, x);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
@@ -676,6 +696,7 @@ __device__ __forceinline__ float polish(float A, float B, float s, float x) {
   return x;
 }
 __device__ __forceinline__ float solve_r(float s, float A, float B) {
+  DDH_EXACT_FP
   if (!(A > 0.0f)) return s;
   const float iA = frcp(A);
   const float a2 = -B * iA, a1 = iA, a0 = -s * iA;
@@ -711,12 +732,14 @@ __device__ __forceinline__ float solve_r(float s, float A, float B) {
 
 // rho'(d)/d of the QGGMRF prior for p = 2:
 //   (1/sig^2) (1 + (q/2) v) / (1 + v)^2,  v = |d/(T sig)|^(2-q)
-// (q = 2 gives v = 1 for every d, the quadratic prior.)  inv_sp is folded
-// into the neighbour weights by the caller.
+// evaluated as u (q/2 + (1 - q/2) u) with u = 1/(1 + v).  (q = 2 gives v = 1
+// for every d, the quadratic prior.)  inv_sp is folded into the neighbour
+// weights by the caller.
 __device__ __forceinline__ float qg_shape(float d, float inv_Ts, float pmq, float qop) {
+  DDH_EXACT_FP
   const float v = pmq > 0.0f ? fexp2(pmq * flog2(fabsf(d) * inv_Ts)) : 1.0f;
-  const float den = 1.0f + v;
-  return __builtin_fmaf(qop, v, 1.0f) * frcp(den * den);
+  const float u = frcp(1.0f + v);
+  return u * __builtin_fmaf(1.0f - qop, u, qop);
 }
 
 // ---------------------------------------------------------------------------
@@ -725,14 +748,30 @@ __device__ __forceinline__ float qg_shape(float d, float inv_Ts, float pmq, floa
 // bit-identical results.  Neighbour order: up, down, left, right, up-left,
 // up-right, down-left, down-right (edges weight 1/6, diagonals 1/12).
 // ---------------------------------------------------------------------------
-// r update of one pixel from its 8 neighbours (ok[e] = neighbour exists)
-__device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], const bool (&ok)[8], float inv_sp,
+// neighbour-existence mask bits of a pixel at the grid border
+enum : int { NB_UP = 1, NB_DN = 2, NB_LF = 4, NB_RT = 8, NB_ALL = 15 };
+__device__ __forceinline__ int nb_mask(int gi, int gj, int N) {
+  return (gi > 0 ? NB_UP : 0) | (gi < N - 1 ? NB_DN : 0) | (gj > 0 ? NB_LF : 0) | (gj < N - 1 ? NB_RT : 0);
+}
+// r update of one pixel from its 8 neighbours.  CHECK: some neighbours may be
+// off the grid (mask bits clear); their weight is zero and their staged value
+// is finite.
+template <bool CHECK>
+__device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], int mask, float inv_sp,
                                          float inv_Ts, float pmq, float qop, float fl) {
+  DDH_EXACT_FP
   float Ae = 0.f, Be = 0.f, Ad = 0.f, Bd = 0.f;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const float sh = ok[e] ? qg_shape(rp - rq[e], inv_Ts, pmq, qop) : 0.f;
-    if (e < 4) {
+    float sh = qg_shape(rp - rq[e], inv_Ts, pmq, qop);
+    if (CHECK) {
+      constexpr int need[8] = {NB_UP, NB_DN, NB_LF, NB_RT, NB_UP | NB_LF, NB_UP | NB_RT, NB_DN | NB_LF, NB_DN | NB_RT};
+      sh = ((mask & need[e]) == need[e]) ? sh : 0.f;
+    }
+    if (e == 0 || e == 4) {  // first term of each sum (shapes are >= +0)
+      (e == 0 ? Ae : Ad) = sh;
+      (e == 0 ? Be : Bd) = sh * rq[e];
+    } else if (e < 4) {
       Ae += sh;
       Be = __builtin_fmaf(sh, rq[e], Be);
     } else {
@@ -748,29 +787,37 @@ __device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8]
 // the pupil and off the grid), P the prior weight of the pupil neighbours
 __device__ __forceinline__ float phi_pixel(const float (&pq)[8], float P, float ka, float tt, float beta2,
                                            float cur) {
+  DDH_EXACT_FP
   const float se = (pq[0] + pq[1]) + (pq[2] + pq[3]);
   const float sd = (pq[4] + pq[5]) + (pq[6] + pq[7]);
   const float Ph = __builtin_fmaf(1.0f / 6.0f, se, (1.0f / 12.0f) * sd);
   const float den = __builtin_fmaf(beta2, P, ka);
   return den > 0.0f ? __builtin_fmaf(ka, tt, beta2 * Ph) * frcp(den) : cur;
 }
-// prior weight of the pupil neighbours of a pupil pixel (di = 2i-N+1, dj = 2j-N+1)
-__device__ __forceinline__ float pupil_nbr_weight(int gi, int gj, int N, float d2) {
-  const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
-  const int ai = abs(di) + 2, aj = abs(dj) + 2;
-  if ((float)(ai * ai + aj * aj) <= d2) return 1.0f;  // farthest diagonal inside => all 8 inside
+// prior weight of the pupil neighbours of a pupil pixel, as twelfths:
+// 2 per edge neighbour and 1 per diagonal neighbour inside the pupil
+__device__ __forceinline__ int pupil_nbr_12(int gi, int gj, int N, float d2) {
   const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
-  float P = 0.f;
+  int n12 = 0;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ii = gi + nb[e][0], jj = gj + nb[e][1];
-    if (ii >= 0 && ii < N && jj >= 0 && jj < N && in_pupil(ii, jj, N, d2)) P += e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f;
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N && in_pupil(ii, jj, N, d2)) n12 += e < 4 ? 2 : 1;
   }
-  return P;
+  return n12;
 }
+__device__ __forceinline__ float pupil_weight_of(int n12) { return (float)n12 * (1.0f / 12.0f); }
 
 constexpr int MS_THREADS = 256;
-enum : unsigned char { F_GRID = 1, F_PUPIL = 2, F_INNER = 4, F_PFULL = 8 };
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [I0, I1)
+template <int I0, int I1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
 
 // Geometry of the halo-tiled sweep: region RH x RW = (TH + 8) x (TW + 8);
 // pass c updates the colour-c pixels of rows/cols [c+1, R-c-1).  Tile origins
@@ -788,34 +835,7 @@ struct MsGeom {
   static constexpr int rounds(int c) { return (n(c) + BT - 1) / BT; }
   static constexpr int slot0(int c) { return c == 0 ? 0 : slot0(c - 1) + rounds(c - 1); }
   static constexpr int SLOTS = rounds(0) + rounds(1) + rounds(2) + rounds(3);
-  static __device__ __forceinline__ int offset(int c, int idx) {
-    const int u = idx / nv(c);
-    return (li0(c) + 2 * u) * RW + lj0(c) + 2 * (idx - u * nv(c));
-  }
 };
-
-template <int RW>
-__device__ __forceinline__ float r_update(const float* sR, const unsigned char* sF, int o, unsigned char f, float s,
-                                          float inv_sp, float inv_Ts, float pmq, float qop, float fl) {
-  constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
-  float rq[8];
-  bool ok[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    rq[e] = sR[o + offs[e]];
-    ok[e] = (f & F_INNER) ? true : (sF[o + offs[e]] & F_GRID) != 0;
-  }
-  return r_pixel(sR[o], s, rq, ok, inv_sp, inv_Ts, pmq, qop, fl);
-}
-
-template <int RW>
-__device__ __forceinline__ float phi_update(const float* sP, int o, float P, float ka, float tt, float beta2) {
-  constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
-  float pq[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) pq[e] = sP[o + offs[e]];
-  return phi_pixel(pq, P, ka, tt, beta2, sP[o]);
-}
 
 // ---------------------------------------------------------------------------
 // k_mstep: one 4-colour sweep of the r and phi M-steps on a TH x TW output
@@ -823,23 +843,24 @@ __device__ __forceinline__ float phi_update(const float* sP, int o, float P, flo
 // updates the colour-c pixels of the region shrunk by c+1, so the inner tile
 // sees exactly the values a whole-grid sweep produces.  All global reads of
 // a block are issued before the first wait.  s = E|g|^2 is computed once per
-// staged pixel; each thread keeps the per-pixel constants (s, kappa, theta~)
-// of the pixels it updates in registers.  Colour(i, j) = (i mod 2) +
-// 2 (j mod 2).  Reads state buffer in = (cur + k) & 1, writes in ^ 1.
-// grid (tiles, streams), block BT (the first pass's pixel count rounded up to
-// whole waves); blocks are remapped so that neighbouring tiles of a stream run
-// on the same XCD (shared L2 for the halo).
+// staged pixel; each thread keeps the per-pixel constants of the pixels it
+// updates (LDS offset, border mask, s, pupil-neighbour weight, kappa, theta~)
+// in registers.  Colour(i, j) = (i mod 2) + 2 (j mod 2).  Reads state buffer
+// in = (cur + k) & 1, writes in ^ 1.  grid (tiles, streams), block BT (the
+// first pass's pixel count rounded up to whole waves); blocks are remapped
+// so that neighbouring tiles of a stream run on the same XCD (shared L2 for
+// the halo).
 // ---------------------------------------------------------------------------
 template <int N, int TH, int TW>
-__global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane,
+__global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane,
                                                               int do_rinit) {
   using G = MsGeom<TH, TW>;
   constexpr int BT = G::BT;
   constexpr int RW = G::RW, RP = G::RP, SLOTS = G::SLOTS;
   constexpr int TPC = N / TW, TPR = N / TH;
   constexpr int TILES = TPC * TPR;
-  __shared__ float sR[RP], sP[RP], sS[RP];
-  __shared__ unsigned char sF[RP];
+  constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
+  __shared__ __align__(16) float sR[RP], sP[RP], sS[RP];
   const int total = TILES * gridDim.y;
   const int L = blockIdx.x + blockIdx.y * TILES;
   const int logical = (total % 8 == 0) ? (L % 8) * (total / 8) + (L / 8) : L;
@@ -856,123 +877,147 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) void k_mstep(StreamDesc* cons
   const float d2 = D.pupil_d2;
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
   // ---- every global read is issued up front: r, |b|^2 and phi of the
-  // region (staging rounds), and (kappa, theta~) of the pupil pixels this
-  // thread updates
-  constexpr int SR = (RP + BT - 1) / BT;
-  const float* bbp = glb(D.bb);
+  // region in 4-pixel vectors (the halo is 4 wide and tile origins are
+  // multiples of 4, so a vector is wholly on or off the grid), and
+  // (kappa, theta~) of the pupil pixels this thread updates.  phi is zero off
+  // the pupil in every state buffer, so it is read unconditionally.
+  constexpr int RW4 = RW / 4, RP4 = G::RH * RW4;
+  constexpr int SR = (RP4 + BT - 1) / BT;
+  const float4* rin4 = reinterpret_cast<const float4*>(rin);
+  const float4* pin4 = reinterpret_cast<const float4*>(pin);
+  const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
   const float2* ktp = glb(D.T);
-  float gr[SR], gb[SR], gph[SR];
+  float4 gr[SR], gb[SR], gph[SR];
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
     const int idx = threadIdx.x + q * BT;
-    const int li = idx / RW, lj = idx - li * RW;
-    const int gi = gi0 + li, gj = gj0 + lj;
-    gr[q] = 0.f;
-    gb[q] = 0.f;
-    gph[q] = 0.f;
-    if (idx < RP && gi >= 0 && gi < N && gj >= 0 && gj < N) {
-      const int pidx = gi * N + gj;
-      gr[q] = rin[pidx];
-      gb[q] = bbp[pidx];
-      if (in_pupil(gi, gj, N, d2)) gph[q] = pin[pidx];
+    const int li = idx / RW4, gi = gi0 + li, gj = gj0 + 4 * (idx - li * RW4);
+    gr[q] = gb[q] = gph[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (idx < RP4 && gi >= 0 && gi < N && gj >= 0 && gj < N) {
+      const int v = (gi * N + gj) / 4;
+      gr[q] = rin4[v];
+      gb[q] = bb4[v];
+      gph[q] = pin4[v];
     }
   }
+  // per own pixel, one packed word: LDS offset (bits 0-15), neighbour mask
+  // (16-19), pupil-neighbour weight in twelfths (20-23), in-pupil flag (24);
+  // -1 when the pixel is off the grid or beyond this pass.  Then kappa and
+  // theta~.  Tiles away from the grid border have every neighbour.
+  const bool border = ti == 0 || ti == TPR - 1 || tj == 0 || tj == TPC - 1;
+  int opk[SLOTS];
   float okap[SLOTS], ott[SLOTS];
-  int oo[SLOTS];
-#define DDH_OWN(C)                                                 \
-  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {   \
-    const int slot = G::slot0(C) + rd;                             \
-    const int idx = threadIdx.x + rd * BT;                         \
-    okap[slot] = 0.f;                                              \
-    ott[slot] = 0.f;                                               \
-    oo[slot] = -1;                                                 \
-    if (idx < G::n(C)) {                                           \
-      const int o = G::offset(C, idx);                             \
-      const int gi = gi0 + o / RW, gj = gj0 + (o - (o / RW) * RW); \
-      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {                \
-        oo[slot] = o;                                              \
-        if (in_pupil(gi, gj, N, d2)) {                             \
-          const float2 kt = ktp[gi * N + gj];                      \
-          okap[slot] = kt.x;                                       \
-          ott[slot] = kt.y;                                        \
-        }                                                          \
-      }                                                            \
-    }                                                              \
-  }
-  DDH_OWN(0) DDH_OWN(1) DDH_OWN(2) DDH_OWN(3)
-#undef DDH_OWN
+  static_for<0, 4>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+#pragma unroll
+    for (int rd = 0; rd < G::rounds(c); ++rd) {
+      const int slot = G::slot0(c) + rd;
+      const int idx = threadIdx.x + rd * BT;
+      const int u = idx / G::nv(c);
+      const int li = G::li0(c) + 2 * u, lj = G::lj0(c) + 2 * (idx - u * G::nv(c));
+      const int gi = gi0 + li, gj = gj0 + lj;
+      const bool own = idx < G::n(c) && (!border || (gi >= 0 && gi < N && gj >= 0 && gj < N));
+      int pk = (li * RW + lj) | ((border ? nb_mask(gi, gj, N) : NB_ALL) << 16);
+      okap[slot] = 0.f;
+      ott[slot] = 0.f;
+      const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
+      const int r2 = __mul24(di, di) + __mul24(dj, dj);
+      if (own && (float)r2 <= d2) {
+        const float2 kt = ktp[gi * N + gj];
+        okap[slot] = kt.x;
+        ott[slot] = kt.y;
+        // the farthest diagonal neighbour inside the disk => all 8 are
+        const bool full = (float)(r2 + 4 * (abs(di) + abs(dj)) + 8) <= d2;
+        pk |= ((full ? 12 : pupil_nbr_12(gi, gj, N, d2)) << 20) | (1 << 24);
+      }
+      opk[slot] = own ? pk : -1;
+    }
+  });
   if (sc[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
-    for (int idx = threadIdx.x; idx < TH * TW; idx += BT) {
-      const int gi = ti * TH + idx / TW, gj = tj * TW + idx % TW;
-      rout[gi * N + gj] = rin[gi * N + gj];
-      pout[gi * N + gj] = pin[gi * N + gj];
+    for (int idx = threadIdx.x; idx < TH * (TW / 4); idx += BT) {
+      const int li = idx / (TW / 4);
+      const int v = ((ti * TH + li) * N + tj * TW) / 4 + (idx - li * (TW / 4));
+      reinterpret_cast<float4*>(rout)[v] = rin4[v];
+      reinterpret_cast<float4*>(pout)[v] = pin4[v];
     }
     return;
   }
   const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
   // ---- stage the region: r after the Eq. (3) initialisation, s = E|g|^2,
-  // phi' and flags
+  // and phi' (zero off the pupil and off the grid)
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
     const int idx = threadIdx.x + q * BT;
-    if (idx < RP) {
-      const int li = idx / RW, lj = idx - li * RW;
-      const int gi = gi0 + li, gj = gj0 + lj;
-      float r = 0.f, sv = 0.f, p = 0.f;
-      unsigned char f = 0;
+    if (idx < RP4) {
+      const int li = idx / RW4, c4 = idx - li * RW4;
+      const int gi = gi0 + li, gj = gj0 + 4 * c4;
+      float r[4] = {0.f, 0.f, 0.f, 0.f}, sv[4] = {0.f, 0.f, 0.f, 0.f}, p[4] = {0.f, 0.f, 0.f, 0.f};
       if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
-        f = F_GRID;
-        if (gi >= 1 && gi <= N - 2 && gj >= 1 && gj <= N - 2) f |= F_INNER;
-        r = do_rinit ? rinit_of(gr[q], gb[q], lam, alpha, fl) : gr[q];
-        sv = second_moment(wiener_of(r, s2), gb[q], s2);
-        const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
-        if ((float)(di * di + dj * dj) <= d2) {
-          f |= F_PUPIL;
-          // the farthest diagonal neighbour inside the disk => all 8 are
-          const int ai = abs(di) + 2, aj = abs(dj) + 2;
-          if ((float)(ai * ai + aj * aj) <= d2) f |= F_PFULL;
-          p = use_plane ? gph[q] - plane_val(c0, c1, c2, gi, gj, N) : gph[q];
+        const float rv[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
+        const float bv[4] = {gb[q].x, gb[q].y, gb[q].z, gb[q].w};
+        const float pv[4] = {gph[q].x, gph[q].y, gph[q].z, gph[q].w};
+        const int di = 2 * gi - N + 1;
+        const int di2 = __mul24(di, di);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          r[e] = do_rinit ? rinit_of(rv[e], bv[e], lam, alpha, fl) : rv[e];
+          sv[e] = second_moment(wiener_of(r[e], s2), bv[e], s2);
+          const int dj = 2 * (gj + e) - N + 1;
+          if ((float)(di2 + __mul24(dj, dj)) <= d2) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
         }
       }
-      sR[idx] = r;
-      sS[idx] = sv;
-      sP[idx] = p;
-      sF[idx] = f;
+      const int o4 = li * RW4 + c4;
+      reinterpret_cast<float4*>(sR)[o4] = make_float4(r[0], r[1], r[2], r[3]);
+      reinterpret_cast<float4*>(sS)[o4] = make_float4(sv[0], sv[1], sv[2], sv[3]);
+      reinterpret_cast<float4*>(sP)[o4] = make_float4(p[0], p[1], p[2], p[3]);
     }
   }
   __syncthreads();
   float os[SLOTS];
 #pragma unroll
-  for (int slot = 0; slot < SLOTS; ++slot) os[slot] = oo[slot] >= 0 ? sS[oo[slot]] : 0.f;
+  for (int slot = 0; slot < SLOTS; ++slot) os[slot] = opk[slot] >= 0 ? sS[opk[slot] & 0xffff] : 0.f;
   const float inv_sp = D.qg_inv_sp, inv_Ts = D.qg_inv_Ts, pmq = D.qg_pmq, qop = D.qg_qop;
   // ---- the four colour passes (same-colour pixels are never neighbours, so
-  // each pass updates its pixels in place)
-#define DDH_PASS(C)                                                                                 \
-  _Pragma("unroll") for (int rd = 0; rd < G::rounds(C); ++rd) {                                    \
-    const int slot = G::slot0(C) + rd;                                                              \
-    const int o = oo[slot];                                                                         \
-    if (o >= 0) {                                                                                   \
-      const unsigned char f = sF[o];                                                                \
-      const float rn = r_update<RW>(sR, sF, o, f, os[slot], inv_sp, inv_Ts, pmq, qop, fl);          \
-      float pn = 0.f;                                                                               \
-      if (f & F_PUPIL) {                                                                            \
-        const int li = o / RW, lj = o - (o / RW) * RW;                                              \
-        const float P = (f & F_PFULL) ? 1.0f : pupil_nbr_weight(gi0 + li, gj0 + lj, N, d2);         \
-        pn = phi_update<RW>(sP, o, P, okap[slot], ott[slot], beta2);                                \
-      }                                                                                             \
-      sR[o] = rn;                                                                                   \
-      if (f & F_PUPIL) sP[o] = pn;                                                                  \
-    }                                                                                               \
-  }                                                                                                 \
-  __syncthreads();
-  DDH_PASS(0) DDH_PASS(1) DDH_PASS(2) DDH_PASS(3)
-#undef DDH_PASS
-  for (int idx = threadIdx.x; idx < TH * TW; idx += BT) {
-    const int li = 4 + idx / TW, lj = 4 + idx % TW;
-    const int o = li * RW + lj;
-    const int gi = gi0 + li, gj = gj0 + lj;
-    rout[gi * N + gj] = sR[o];
-    pout[gi * N + gj] = (sF[o] & F_PUPIL) ? sP[o] : 0.0f;
+  // each pass updates its pixels in place).  The neighbour-mask test is
+  // compiled only into the path of the tiles at the grid border, a
+  // block-uniform branch.
+  auto passes = [&](auto check) {
+    constexpr bool CHECK = decltype(check)::value;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int rd = 0; rd < G::rounds(c); ++rd) {
+        const int slot = G::slot0(c) + rd;
+        const int pk = opk[slot];
+        if (pk >= 0) {
+          const int o = pk & 0xffff;
+          float rq[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) rq[e] = sR[o + offs[e]];
+          const float rn = r_pixel<CHECK>(sR[o], os[slot], rq, (pk >> 16) & NB_ALL, inv_sp, inv_Ts, pmq, qop, fl);
+          if (pk & (1 << 24)) {
+            float pq[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) pq[e] = sP[o + offs[e]];
+            sP[o] = phi_pixel(pq, pupil_weight_of((pk >> 20) & 15), okap[slot], ott[slot], beta2, sP[o]);
+          }
+          sR[o] = rn;
+        }
+      }
+      __syncthreads();
+    }
+  };
+  if (border)
+    passes(std::true_type{});
+  else
+    passes(std::false_type{});
+  // ---- the inner tile back to the output buffers, 4-pixel vectors
+  for (int idx = threadIdx.x; idx < TH * (TW / 4); idx += BT) {
+    const int li = idx / (TW / 4), c4 = idx - li * (TW / 4);
+    const int o4 = (4 + li) * RW4 + 1 + c4;
+    const int v = ((ti * TH + li) * N + tj * TW) / 4 + c4;
+    reinterpret_cast<float4*>(rout)[v] = reinterpret_cast<const float4*>(sR)[o4];
+    reinterpret_cast<float4*>(pout)[v] = reinterpret_cast<const float4*>(sP)[o4];
   }
 }
 
@@ -1033,11 +1078,10 @@ __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) 
   // ---- r update
   const float s2 = D.sigma2;
   const float s = second_moment(wiener_of(rp, s2), bb, s2);
-  const bool ok[8] = {up, dn, lf, rt, up && lf, up && rt, dn && lf, dn && rt};
-  rw[p] = r_pixel(rp, s, rq, ok, D.qg_inv_sp, D.qg_inv_Ts, D.qg_pmq, D.qg_qop, D.r_floor);
+  rw[p] = r_pixel<true>(rp, s, rq, nb_mask(gi, gj, N), D.qg_inv_sp, D.qg_inv_Ts, D.qg_pmq, D.qg_qop, D.r_floor);
   // ---- phi update
   if (pup) {
-    const float P = pupil_nbr_weight(gi, gj, N, d2);
+    const float P = pupil_weight_of(pupil_nbr_12(gi, gj, N, d2));
     pw[p] = phi_pixel(pq, P, kt.x, kt.y, 2.0f * D.beta, pw[p]);
   }
 }
