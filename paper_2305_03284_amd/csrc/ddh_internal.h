@@ -43,6 +43,7 @@ struct StreamDesc {
   float qg_pmq;        // p - q
   float qg_qop;        // q / p
   float qg_pm2;        // p - 2
+  float qg_lc;         // (p - q) log2(1 / (T sigma))
   int pending;         // buffer advance of the last frame, applied by the next k_begin
   // pupil moments for the plane fit (exact, host-computed):
   // n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with di = i-c, dj = j-c

@@ -673,7 +673,9 @@ __device__ __forceinline__ float fcos_rev(float rev) { return __builtin_amdgcn_c
 //   h(rho) = log rho + s/rho + (A/2) rho^2 - B rho
 // via the stationarity cubic A rho^3 - B rho^2 + rho - s = 0 (all real roots
 // are positive for s > 0, A > 0, B >= 0).  One real root: Cardano; three:
-// trigonometric form; each root polished by guarded Newton steps.  With three
+// trigonometric form; each root polished by guarded Newton steps (one for the
+// Cardano root, whose FP32 error is within a few ulp after one step; two for
+// the trigonometric roots).  With three
 // roots the middle one is a local maximum of h; the outer two are compared by
 // h(rho1) - h(rho3) written as one difference; ties take the smaller root.
 // ---------------------------------------------------------------------------
@@ -681,11 +683,12 @@ __device__ __forceinline__ float cubic_f(float A, float B, float s, float x) {
   DDH_EXACT_FP
   return __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A, x, -B), x, 1.0f), x, -s);
 }
+template <int IT>
 __device__ __forceinline__ float polish(float A, float B, float s, float x) {
   DDH_EXACT_FP
   float f = cubic_f(A, B, s, x);
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < IT; ++it) {
     const float fp = __builtin_fmaf(__builtin_fmaf(3.0f * A, x, -2.0f * B), x, 1.0f);
     const float xn = x - f * frcp(fp);
     const float fn = cubic_f(A, B, s, xn);
@@ -710,7 +713,7 @@ __device__ __forceinline__ float solve_r(float s, float A, float B) {
     const float t = (u != 0.0f) ? u - p * frcp(3.0f * u) : 0.0f;
     float x = t + sh;
     if (!(x > 0.0f) || !isfinite(x)) x = s;
-    return polish(A, B, s, x);
+    return polish<1>(A, B, s, x);
   }
   const float m = fsqrt(-p * (1.0f / 3.0f));
   float arg = (1.5f * q * frcp(p)) * fsqrt(-3.0f * frcp(p));
@@ -722,8 +725,8 @@ __device__ __forceinline__ float solve_r(float s, float A, float B) {
   const float x3 = 2.0f * m * fcos_rev(th - (2.0f / 3.0f)) + sh;
   float lo = fminf(fminf(x1, x2), x3), hi = fmaxf(fmaxf(x1, x2), x3);
   if (!(lo > 0.0f)) lo = fminf(s, hi);
-  lo = polish(A, B, s, lo);
-  hi = polish(A, B, s, hi);
+  lo = polish<2>(A, B, s, lo);
+  hi = polish<2>(A, B, s, hi);
   // h(lo) - h(hi) as one difference
   const float dh = 0.69314718055994531f * flog2(lo * frcp(hi)) + s * (hi - lo) * frcp(lo * hi) +
                    (lo - hi) * (0.5f * A * (lo + hi) - B);
@@ -732,12 +735,13 @@ __device__ __forceinline__ float solve_r(float s, float A, float B) {
 
 // rho'(d)/d of the QGGMRF prior for p = 2:
 //   (1/sig^2) (1 + (q/2) v) / (1 + v)^2,  v = |d/(T sig)|^(2-q)
-// evaluated as u (q/2 + (1 - q/2) u) with u = 1/(1 + v).  (q = 2 gives v = 1
-// for every d, the quadratic prior.)  inv_sp is folded into the neighbour
-// weights by the caller.
-__device__ __forceinline__ float qg_shape(float d, float inv_Ts, float pmq, float qop) {
+// evaluated as u (q/2 + (1 - q/2) u) with u = 1/(1 + v) and
+// log2 v = (2-q) log2|d| + lc, lc = (2-q) log2(1/(T sig)).  (q = 2 gives
+// v = 1 for every d, the quadratic prior.)  inv_sp is folded into the
+// neighbour weights by the caller.
+__device__ __forceinline__ float qg_shape(float d, float lc, float pmq, float qop) {
   DDH_EXACT_FP
-  const float v = pmq > 0.0f ? fexp2(pmq * flog2(fabsf(d) * inv_Ts)) : 1.0f;
+  const float v = pmq > 0.0f ? fexp2(__builtin_fmaf(pmq, flog2(fabsf(d)), lc)) : 1.0f;
   const float u = frcp(1.0f + v);
   return u * __builtin_fmaf(1.0f - qop, u, qop);
 }
@@ -758,12 +762,12 @@ __device__ __forceinline__ int nb_mask(int gi, int gj, int N) {
 // is finite.
 template <bool CHECK>
 __device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], int mask, float inv_sp,
-                                         float inv_Ts, float pmq, float qop, float fl) {
+                                         float lc, float pmq, float qop, float fl) {
   DDH_EXACT_FP
   float Ae = 0.f, Be = 0.f, Ad = 0.f, Bd = 0.f;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    float sh = qg_shape(rp - rq[e], inv_Ts, pmq, qop);
+    float sh = qg_shape(rp - rq[e], lc, pmq, qop);
     if (CHECK) {
       constexpr int need[8] = {NB_UP, NB_DN, NB_LF, NB_RT, NB_UP | NB_LF, NB_UP | NB_RT, NB_DN | NB_LF, NB_DN | NB_RT};
       sh = ((mask & need[e]) == need[e]) ? sh : 0.f;
@@ -976,7 +980,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   float os[SLOTS];
 #pragma unroll
   for (int slot = 0; slot < SLOTS; ++slot) os[slot] = opk[slot] >= 0 ? sS[opk[slot] & 0xffff] : 0.f;
-  const float inv_sp = D.qg_inv_sp, inv_Ts = D.qg_inv_Ts, pmq = D.qg_pmq, qop = D.qg_qop;
+  const float inv_sp = D.qg_inv_sp, lc = D.qg_lc, pmq = D.qg_pmq, qop = D.qg_qop;
   // ---- the four colour passes (same-colour pixels are never neighbours, so
   // each pass updates its pixels in place).  The neighbour-mask test is
   // compiled only into the path of the tiles at the grid border, a
@@ -994,7 +998,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
           float rq[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) rq[e] = sR[o + offs[e]];
-          const float rn = r_pixel<CHECK>(sR[o], os[slot], rq, (pk >> 16) & NB_ALL, inv_sp, inv_Ts, pmq, qop, fl);
+          const float rn = r_pixel<CHECK>(sR[o], os[slot], rq, (pk >> 16) & NB_ALL, inv_sp, lc, pmq, qop, fl);
           if (pk & (1 << 24)) {
             float pq[8];
 #pragma unroll
@@ -1078,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) 
   // ---- r update
   const float s2 = D.sigma2;
   const float s = second_moment(wiener_of(rp, s2), bb, s2);
-  rw[p] = r_pixel<true>(rp, s, rq, nb_mask(gi, gj, N), D.qg_inv_sp, D.qg_inv_Ts, D.qg_pmq, D.qg_qop, D.r_floor);
+  rw[p] = r_pixel<true>(rp, s, rq, nb_mask(gi, gj, N), D.qg_inv_sp, D.qg_lc, D.qg_pmq, D.qg_qop, D.r_floor);
   // ---- phi update
   if (pup) {
     const float P = pupil_weight_of(pupil_nbr_12(gi, gj, N, d2));

@@ -386,6 +386,7 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.qg_inv_sp = (float)(1.0 / ((double)p->qg_sigma * (double)p->qg_sigma));
   h.qg_inv_Ts = (float)(1.0 / ((double)p->qg_T * (double)p->qg_sigma));
   h.qg_pmq = p->qg_p - p->qg_q;
+  h.qg_lc = (float)(((double)p->qg_p - (double)p->qg_q) * std::log2(1.0 / ((double)p->qg_T * (double)p->qg_sigma)));
   h.qg_qop = p->qg_q / p->qg_p;
   h.qg_pm2 = p->qg_p - 2.0f;
   // pupil moments (exact sums over integer coordinates, in double)
