@@ -33,7 +33,7 @@ struct StreamDesc {
   float* part;         // stats partials, PART_STRIDE floats per stats block
   float* scal;         // SC_COUNT floats
   int N;
-  int cur;             // index of the current state buffer (advanced on the device)
+  int cur;             // index of the current state buffer at the start of a frame
   float pupil_d2;      // diameter^2 (pixel (i,j) in pupil iff (2i-N+1)^2+(2j-N+1)^2 <= d2)
   float sigma2, lam, alpha, beta, r_floor;
   float qg_p, qg_q, qg_T, qg_sigma;
@@ -44,7 +44,6 @@ struct StreamDesc {
   float qg_qop;        // q / p
   float qg_pm2;        // p - 2
   float qg_lc;         // (p - q) log2(1 / (T sigma))
-  int pending;         // buffer advance of the last frame, applied by the next k_begin
   // pupil moments for the plane fit (exact, host-computed):
   // n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with di = i-c, dj = j-c
   double mom[6];
@@ -70,8 +69,14 @@ constexpr int TWIDDLE_TOTAL = 960;
 // dptrs: device array of device descriptor pointers for the streams of one
 // launch (one grid size N for the per-N kernels).  k: EM iteration index
 // within the frame; the state buffer read is (cur + k) & 1.
-hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, int count, int iters, hipStream_t st);
-hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st);
+// Frame start: ys[i] is stream i's frame and curs[i] its current state buffer
+// (host-tracked).  launch_begin stores both in the descriptors; launch_stats
+// with ys != nullptr stores them itself (the later kernels of the frame read
+// them from the descriptors), with ys == nullptr it reads them there.
+hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const int* curs, int count,
+                        hipStream_t st);
+hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, const float2* const* ys,
+                        const int* curs, hipStream_t st);
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st);
 hipError_t launch_row1(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
                        int fin, int with_phi, const TileConfig& tc, hipStream_t st);

@@ -333,20 +333,22 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red /* >= NV*16
 }
 
 // ---------------------------------------------------------------------------
-// k_begin: start of a frame.  Store this step's frame pointers, apply the
-// state-buffer advance of the previous frame (its EM iteration count) and
-// record this frame's count for the next call.
+// Frame start arguments: this frame's y and current state buffer per stream
+// of a launch (at most 64 streams per launch).
 // ---------------------------------------------------------------------------
-struct YArgs {
-  const float2* p[64];
+constexpr int FRAME_ARGS_MAX = 64;
+struct FrameArgs {
+  const float2* y[FRAME_ARGS_MAX];
+  int cur[FRAME_ARGS_MAX];
 };
-__global__ void k_begin(StreamDesc* const* dptrs, YArgs a, int count, int iters) {
+// k_begin: store the frame arguments in the descriptors (used before a
+// replayed graph, whose kernels read them there).  grid 1, block 64
+__global__ void k_begin(StreamDesc* const* dptrs, FrameArgs a, int count) {
   const int i = threadIdx.x;
   if (i < count) {
     const auto d = glb(dptrs[i]);
-    d->y = a.p[i];
-    d->cur = (d->cur + d->pending) & 1;
-    d->pending = iters;
+    d->y = a.y[i];
+    d->cur = a.cur[i];
   }
 }
 
@@ -356,17 +358,22 @@ __global__ void k_begin(StreamDesc* const* dptrs, YArgs a, int count, int iters)
 // grid (N*N/4096, streams), block 256
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int with_phi) {
+__global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int with_phi, FrameArgs a, int use_args) {
   const auto& D = desc_ref(dptrs[blockIdx.y]);
   __shared__ float red[6 * 16];
   const int base = blockIdx.x * STATS_PIX_PER_BLOCK;
   constexpr float c = 0.5f * (float)(N - 1);
   float2 v[16];
   float ph[16];
-  const float* phi = glb(D.phi[D.cur]);
+  // frame start: from the arguments (block 0 stores them in the descriptor
+  // for the later kernels; no block of this launch reads them there) or from
+  // the descriptor
+  const float2* yv = use_args ? glb(a.y[blockIdx.y]) : glb(D.y);
+  const int cur = use_args ? a.cur[blockIdx.y] : D.cur;
+  const float* phi = glb(D.phi[cur]);
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = glb(D.y)[base + k * 256 + threadIdx.x];
+  for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + threadIdx.x];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int idx = base + k * 256 + threadIdx.x;
@@ -399,6 +406,11 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int wit
       ps[2] += ((float)j - c) * p;
     }
     block_sum<3>(ps, red);
+  }
+  if (use_args && blockIdx.x == 0 && threadIdx.x == 0) {
+    const auto d = glb(dptrs[blockIdx.y]);
+    d->y = a.y[blockIdx.y];
+    d->cur = cur;
   }
   if (threadIdx.x == 0) {
     float* out = glb(D.part) + blockIdx.x * PART_STRIDE;
@@ -1350,22 +1362,44 @@ __global__ void k_copy(float* dst, const float* src, long long n) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, int count, int iters, hipStream_t st) {
-  for (int off = 0; off < count; off += 64) {
-    YArgs a{};
-    const int n = count - off < 64 ? count - off : 64;
-    for (int i = 0; i < n; ++i) a.p[i] = ys[off + i];
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, dptrs + off, a, n, iters);
+hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const int* curs, int count,
+                        hipStream_t st) {
+  for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
+    FrameArgs a{};
+    const int n = count - off < FRAME_ARGS_MAX ? count - off : FRAME_ARGS_MAX;
+    for (int i = 0; i < n; ++i) {
+      a.y[i] = ys[off + i];
+      a.cur[i] = curs[off + i];
+    }
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, dptrs + off, a, n);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st) {
-#define DDH_X(NN)                                                                                              \
-  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, count), dim3(256), 0, st, dptrs, with_phi); \
-  return hipGetLastError();
-  DDH_DISPATCH_N(N, DDH_X)
+hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, const float2* const* ys,
+                        const int* curs, hipStream_t st) {
+  for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
+    FrameArgs a{};
+    const int n = count - off < FRAME_ARGS_MAX ? count - off : FRAME_ARGS_MAX;
+    if (ys)
+      for (int i = 0; i < n; ++i) {
+        a.y[i] = ys[off + i];
+        a.cur[i] = curs[off + i];
+      }
+#define DDH_X(NN)                                                                                  \
+  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, n), dim3(256), 0, st, dptrs + off, \
+                     with_phi, a, ys ? 1 : 0);                                                      \
+  break;
+    switch (N) {
+      case 64: DDH_X(64)
+      case 128: DDH_X(128)
+      case 256: DDH_X(256)
+      case 512: DDH_X(512)
+      default: return hipErrorInvalidValue;
+    }
 #undef DDH_X
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st) {

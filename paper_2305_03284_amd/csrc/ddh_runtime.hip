@@ -183,7 +183,9 @@ struct ddh_batch_s {
   int device = 0;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
+  bool capturing = false;             // enqueueing into the graph capture (frame start from descriptors)
   std::vector<const float2*> yord;
+  std::vector<int> curord;       // host parity of each stream, in descriptor order
   // timing
   bool timing = false;
   struct Rec {
@@ -205,10 +207,13 @@ namespace {
 // around every launch.
 template <class OnLaunch>
 int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int total, int n_k, int mode,
-                  hipStream_t st, OnLaunch&& around) {
+                  hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr) {
   hipError_t e;
   for (const Group& g : groups) {
-    e = around(KK_STATS, [&] { return launch_stats(dptrs + g.off, g.count, g.N, mode, st); });
+    e = around(KK_STATS, [&] {
+      return launch_stats(dptrs + g.off, g.count, g.N, mode, ys ? ys + g.off : nullptr, ys ? curs + g.off : nullptr,
+                          st);
+    });
     if (e != hipSuccess) return hip_fail(e, "launch_stats");
   }
   const int iters = mode ? n_k : 1;
@@ -257,10 +262,11 @@ int set_device_of(int dev) {
 int single_step(ddh_stream_t s, const void* y, hipStream_t st, int mode) {
   const float2* yp = static_cast<const float2*>(y);
   const int iters = mode ? s->prm.n_k : 1;
-  hipError_t e = launch_begin(s->dptr, &yp, 1, iters, st);
-  if (e != hipSuccess) return hip_fail(e, "launch_begin");
   std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
   if (mode && s->use_graph) {
+    // the replayed graph reads the frame start from the descriptor
+    hipError_t e = launch_begin(s->dptr, &yp, &s->parity, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "launch_begin");
     if (!s->gexec) {
       hipGraph_t graph = nullptr;
       DDH_CHECK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
@@ -280,7 +286,7 @@ int single_step(ddh_stream_t s, const void* y, hipStream_t st, int mode) {
     }
     DDH_CHECK(hipGraphLaunch(s->gexec, st));
   } else {
-    int rc = enqueue_frame(s->dptr, g, 1, s->prm.n_k, mode, st, NoTiming{});
+    int rc = enqueue_frame(s->dptr, g, 1, s->prm.n_k, mode, st, NoTiming{}, &yp, &s->parity);
     if (rc != DDH_OK) return rc;
   }
   s->parity = (s->parity + iters) & 1;
@@ -372,7 +378,6 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.scal = (float*)(mem + o_scal);
   h.N = N;
   h.cur = 0;
-  h.pending = 0;
   h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
   h.sigma2 = p->sigma_w2;
   h.lam = p->lambda;
@@ -526,9 +531,7 @@ int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream) {
   if (!y || !U) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const float2* yp = static_cast<const float2*>(y);
-  hipError_t e = launch_begin(s->dptr, &yp, 1, 0, st);
-  if (e != hipSuccess) return hip_fail(e, "begin");
-  e = launch_stats(s->dptr, 1, s->N, 0, st);
+  hipError_t e = launch_stats(s->dptr, 1, s->N, 0, &yp, &s->parity, st);
   if (e != hipSuccess) return hip_fail(e, "stats");
   e = launch_finalize(s->dptr, 1, 0, st);
   if (e != hipSuccess) return hip_fail(e, "finalize");
@@ -650,6 +653,7 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
     ln.count = (int)order.size() - ln.off;
   }
   b->yord.assign(count, nullptr);
+  b->curord.assign(count, 0);
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
   if (e != hipSuccess) {
     delete b;
@@ -734,11 +738,13 @@ static int drain_timing(ddh_batch_t b) {
 // Fork the lanes off stream st, enqueue each lane's chain on its own stream,
 // join them back into st (capturable: the graph then has parallel branches).
 static int enqueue_lanes(ddh_batch_t b, hipStream_t st) {
-  if (b->lanes.size() == 1) return enqueue_frame(b->dptrs, b->lanes[0].groups, b->lanes[0].count, b->n_k, 1, st, NoTiming{});
+  const float2* const* ys = b->capturing ? nullptr : b->yord.data();
+  const int* cs = b->curord.data();
+  if (b->lanes.size() == 1) return enqueue_frame(b->dptrs, b->lanes[0].groups, b->lanes[0].count, b->n_k, 1, st, NoTiming{}, ys, cs);
   DDH_CHECK(hipEventRecord(b->fork, st));
   for (Lane& ln : b->lanes) {
     DDH_CHECK(hipStreamWaitEvent(ln.s, b->fork, 0));
-    int rc = enqueue_frame(b->dptrs, ln.groups, ln.count, b->n_k, 1, ln.s, NoTiming{});
+    int rc = enqueue_frame(b->dptrs, ln.groups, ln.count, b->n_k, 1, ln.s, NoTiming{}, ys, cs);
     if (rc != DDH_OK) return rc;
     DDH_CHECK(hipEventRecord(ln.join, ln.s));
   }
@@ -754,7 +760,10 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
     if (!y[i]) return DDH_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  for (int i = 0; i < b->total; ++i) b->yord[b->pos[i]] = static_cast<const float2*>(y[i]);
+  for (int i = 0; i < b->total; ++i) {
+    b->yord[b->pos[i]] = static_cast<const float2*>(y[i]);
+    b->curord[b->pos[i]] = b->streams[i]->parity;
+  }
   if (b->timing && b->recs.size() > 4096) {
     int rc = drain_timing(b);
     if (rc != DDH_OK) return rc;
@@ -771,18 +780,21 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
     b->recs.push_back({kind, a, c});
     return e;
   };
-  hipError_t e = timed(KK_BEGIN, [&] { return launch_begin(b->dptrs, b->yord.data(), b->total, b->n_k, st); });
-  if (e != hipSuccess) return hip_fail(e, "launch_begin");
   const bool graph = (b->flags & DDH_BATCH_GRAPH) && !b->timing;
   if (b->timing) {
     // per-kernel timing: every lane's launches in sequence on the caller's stream
-    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed);
+    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed, b->yord.data(), b->curord.data());
     if (rc != DDH_OK) return rc;
   } else if (graph) {
+    // the replayed graph reads the frame start from the descriptors
+    hipError_t e = launch_begin(b->dptrs, b->yord.data(), b->curord.data(), b->total, st);
+    if (e != hipSuccess) return hip_fail(e, "launch_begin");
     if (!b->gexec) {
       hipGraph_t g = nullptr;
       DDH_CHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      b->capturing = true;
       int rc = enqueue_lanes(b, b->cap);
+      b->capturing = false;
       hipError_t ec = hipStreamEndCapture(b->cap, &g);
       if (rc != DDH_OK) {
         if (g) (void)hipGraphDestroy(g);
