@@ -51,6 +51,11 @@ def parse():
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     p.add_argument("--graph", action="store_true", help="replay the batched step as a HIP graph (eager launches "
                    "are the default: they measured faster)")
+    p.add_argument("--serve", action="store_true", help="instead: the continuous-batching request loop (32 streams "
+                   "at N in {128,256}, Poisson arrivals) against the one-frame-at-a-time loop")
+    p.add_argument("--serve-rate", type=float, default=2000.0, help="aggregate frame arrival rate (Hz)")
+    p.add_argument("--serve-frames", type=int, default=40, help="frames per stream")
+    p.add_argument("--serve-budget", type=float, default=0.75, help="memory budget as a fraction of all streams' bytes")
     return p.parse_args()
 
 
@@ -138,6 +143,70 @@ def oracle_baseline(specs, frames, n_frames_cpu):
                       f"FP64 NumPy, 1 thread, {dt:.1f} s"}
 
 
+def serve_main(args):
+    """Serving workload: 32 streams, N in {128, 256} (1:1, seeded), frames
+    arriving by a Poisson process at --serve-rate aggregate, streams starting
+    within the first 50 ms, --serve-frames frames each (8 distinct frames per
+    stream, cycled, resident on the device), 1 EM iteration per frame, memory
+    budget --serve-budget of all streams' bytes (so later streams wait for
+    admission).  The continuous-batching loop and the one-frame-at-a-time loop
+    run the same arrival trace with a budget that holds every stream, with the
+    smaller budget, at ten times the rate, and with every frame arriving at
+    t = 0 (saturation throughput)."""
+    import torch
+    import paper_2305_03284_amd as D
+    import ddh_synth as synth
+    from paper_2305_03284_amd.serve import ServeLoop, latency_stats, poisson_requests
+    specs = synth.batch_specs(sizes_ratio=((128, 1), (256, 1)), count=32, config_id=4)
+    sims, frames = make_inputs(specs, 8)
+    dev_frames = [[torch.from_numpy(f).cuda() for f in fr] for fr in frames]
+    truth = [[torch.from_numpy(sm.phase(n).astype(np.float32)).cuda() for n in range(8)] for sm in sims]
+    keys = list(range(len(specs)))
+    nbytes = {k: D.stream_bytes(specs[k].N) for k in keys}
+    budget = int(args.serve_budget * sum(nbytes.values()))
+    out = {"metric": "frame latency, continuous-batching request loop", "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"32 streams, N in {{128,256}} 1:1, Poisson arrivals {args.serve_rate:.0f} Hz "
+                                  f"aggregate, {args.serve_frames} frames per stream, N_k=1",
+                      "small_budget_bytes": budget, "all_streams_bytes": sum(nbytes.values()), "depth": 2}}
+    total_bytes = sum(nbytes.values())
+    runs = [("trace", args.serve_rate, total_bytes), ("trace_budget", args.serve_rate, budget),
+            ("trace_10x", 10 * args.serve_rate, total_bytes), ("saturation", None, total_bytes)]
+    for label, rate, bud in runs:
+        rate_reqs = poisson_requests(keys, rate or args.serve_rate, args.serve_frames, seed=4,
+                                     start_spread_s=0.0 if rate is None else 0.05)
+        if rate is None:  # every frame ready at t = 0
+            for r in rate_reqs:
+                r.t_arrival = 0.0
+        res = {"arrival_hz": rate, "budget_bytes": bud}
+        for plain in (False, True):
+            reqs = [type(r)(r.t_arrival, r.key, r.index, r.last, dev_frames[r.key][r.index % 8]) for r in rate_reqs]
+            finals = {}
+
+            def make_stream(k):
+                return D.Stream(specs[k].N, gpu_params(D, specs[k].N, sims[k].sigma_w2))
+
+            def on_retire(k, s):  # asynchronous copies; Strehl is taken after the run
+                finals[k] = (s.reflectance(), s.phase())
+
+            loop = ServeLoop(bud, max_batch=len(keys), depth=2, plain=plain)
+            done = loop.run(reqs, make_stream, nbytes.__getitem__, on_retire)
+            st = latency_stats(done)
+            strehl = []
+            for k, (r_fin, p_fin) in finals.items():
+                probe = make_stream(k)
+                probe.set_state(r_fin, p_fin, args.serve_frames)
+                strehl.append(probe.strehl(truth[k][(args.serve_frames - 1) % 8]))
+                probe.close()
+            st["mean_strehl"] = float(np.mean(strehl))
+            res["plain_one_at_a_time" if plain else "continuous_batching"] = {k: round(v, 4) for k, v in st.items()}
+        out[label] = res
+    tr = out["trace"]["continuous_batching"]
+    out.update({"p50_ms": tr["p50_ms"], "p99_ms": tr["p99_ms"], "frames_per_s": tr["frames_per_s"],
+                "mean_strehl": tr["mean_strehl"]})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,6 +217,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        serve_main(args)
+        return
     import paper_2305_03284_amd as D
     import ddh_synth as synth
 

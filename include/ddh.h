@@ -175,6 +175,33 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 
+/* --------------------------------------------------------------- serving */
+
+/* Continuous batching: a server advances, in one call, whichever distinct
+ * streams have a frame ready, in any mix of N and n_k, the set changing from
+ * call to call (streams are admitted and retired between calls).  Per-stream
+ * numerics are those of ddh_step: a stream gives the same result alone and in
+ * any mix.  The server owns a device list of max_streams descriptor pointers
+ * (8 bytes each) on the current device; it does not own the streams.  Calls
+ * on one server must all use the HIP stream of its first call (DDH_ESTATE
+ * otherwise), so that they run in order: a stream may then appear again in
+ * the next call while this one is still on the GPU. */
+typedef struct ddh_server_s* ddh_server_t;
+int ddh_server_create(int max_streams, ddh_server_t* out);
+
+/* Device bytes that ddh_init_stream allocates for a stream of grid size N
+ * (state, work buffers and descriptor; the twiddle tables are shared per
+ * device).  For admission by memory budget. */
+int ddh_stream_bytes(int N, unsigned long long* bytes);
+int ddh_server_destroy(ddh_server_t s);
+
+/* One DDH frame on each of `count` (0..max_streams) distinct streams.
+ * streams: host array of handles; y: host array of device pointers to their
+ * frames (N*N complex64 each).  Both host arrays may be reused once the call
+ * returns.  DDH_EINVAL for a repeated stream or a null frame. */
+int ddh_server_step(ddh_server_t s, const ddh_stream_t* streams, const void* const* y, int count,
+                    void* hip_stream);
+
 /* ---------------------------------------------------------- FFT (a3, a6) */
 
 /* Batched unitary 2D DFT of `count` N x N complex64 images (device pointers,

@@ -54,6 +54,11 @@ SIGNATURES = {
     "ddh_batch_set_timing": (_c_int, [_c_void_p, _c_int]),
     "ddh_batch_stage_times": (_c_int, [_c_void_p, ctypes.POINTER(_c_double), ctypes.POINTER(_c_ll),
                                        ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_c_int)]),
+    "ddh_server_create": (_c_int, [_c_int, ctypes.POINTER(_c_void_p)]),
+    "ddh_stream_bytes": (_c_int, [_c_int, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "ddh_server_destroy": (_c_int, [_c_void_p]),
+    "ddh_server_step": (_c_int, [_c_void_p, ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int,
+                                 _c_void_p]),
     "ddh_fft2": (_c_int, [_c_int, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p]),
     "ddh_set_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
     "ddh_get_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
@@ -266,6 +271,55 @@ class Batch:
             pass
 
 
+def stream_bytes(N: int) -> int:
+    """Device bytes one stream of grid size N holds (ddh_stream_bytes)."""
+    b = ctypes.c_ulonglong()
+    _check(lib().ddh_stream_bytes(int(N), ctypes.byref(b)), "ddh_stream_bytes")
+    return int(b.value)
+
+
+class Server:
+    """Continuous batching: each call advances whichever distinct streams have
+    a frame ready, the set changing from call to call (``ddh_server_step``)."""
+
+    def __init__(self, max_streams: int):
+        h = ctypes.c_void_p()
+        _check(lib().ddh_server_create(int(max_streams), ctypes.byref(h)), "ddh_server_create")
+        self._h = h
+        self.max_streams = int(max_streams)
+        self._s = (ctypes.c_void_p * self.max_streams)()
+        self._y = (ctypes.c_void_p * self.max_streams)()
+
+    def step(self, streams, ys) -> None:
+        if len(ys) != len(streams):
+            raise ValueError("one frame per stream")
+        if len(streams) > self.max_streams:
+            raise ValueError("more streams than the server holds")
+        for i, (y, s) in enumerate(zip(ys, streams)):
+            _check_frame(y, s.N)
+            self._s[i] = s.handle.value
+            self._y[i] = y.data_ptr()
+        _check(lib().ddh_server_step(self._h, self._s, self._y, len(streams), _stream_ptr()), "ddh_server_step")
+
+    def step_ptrs(self, streams, ptrs) -> None:
+        """Like step() with raw device pointers (already validated by the caller)."""
+        for i, (s, p) in enumerate(zip(streams, ptrs)):
+            self._s[i] = s.handle.value
+            self._y[i] = p
+        _check(lib().ddh_server_step(self._h, self._s, self._y, len(streams), _stream_ptr()), "ddh_server_step")
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().ddh_server_destroy(self._h), "ddh_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def fft2(x, inverse: bool = False):
     """Batched unitary 2-D DFT of a contiguous complex64 CUDA tensor (..., N, N)."""
     torch = _torch()
@@ -301,5 +355,5 @@ def autotune(N: int, count: int):
     return tuple(cfg), tuple(us)
 
 
-__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

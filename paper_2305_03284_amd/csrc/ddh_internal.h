@@ -72,11 +72,14 @@ constexpr int TWIDDLE_TOTAL = 960;
 // Frame start: ys[i] is stream i's frame and curs[i] its current state buffer
 // (host-tracked).  launch_begin stores both in the descriptors; launch_stats
 // with ys != nullptr stores them itself (the later kernels of the frame read
-// them from the descriptors), with ys == nullptr it reads them there.
+// them from the descriptors), with ys == nullptr it reads them there.  With
+// ds != nullptr (host array of the streams' device descriptor pointers)
+// launch_stats also fills the device list dptrs[0..count) for the later
+// kernels of the frame.
 hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const int* curs, int count,
                         hipStream_t st);
 hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, const float2* const* ys,
-                        const int* curs, hipStream_t st);
+                        const int* curs, StreamDesc* const* ds, hipStream_t st);
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st);
 hipError_t launch_row1(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
                        int fin, int with_phi, const TileConfig& tc, hipStream_t st);

@@ -340,6 +340,7 @@ constexpr int FRAME_ARGS_MAX = 64;
 struct FrameArgs {
   const float2* y[FRAME_ARGS_MAX];
   int cur[FRAME_ARGS_MAX];
+  StreamDesc* d[FRAME_ARGS_MAX];  // descriptors, when the launch's device list is filled here
 };
 // k_begin: store the frame arguments in the descriptors (used before a
 // replayed graph, whose kernels read them there).  grid 1, block 64
@@ -357,9 +358,13 @@ __global__ void k_begin(StreamDesc* const* dptrs, FrameArgs a, int count) {
 // registers), and the plane-fit sums of phi over the pupil.
 // grid (N*N/4096, streams), block 256
 // ---------------------------------------------------------------------------
+// use_args: 0 frame start from the descriptor; 1 from the arguments; 2 from
+// the arguments, and the descriptor pointers too, which block 0 of each
+// stream also stores in the device list dptrs for the later kernels.
 template <int N>
-__global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int with_phi, FrameArgs a, int use_args) {
-  const auto& D = desc_ref(dptrs[blockIdx.y]);
+__global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi, FrameArgs a, int use_args) {
+  StreamDesc* const dp = use_args == 2 ? a.d[blockIdx.y] : dptrs[blockIdx.y];
+  const auto& D = desc_ref(dp);
   __shared__ float red[6 * 16];
   const int base = blockIdx.x * STATS_PIX_PER_BLOCK;
   constexpr float c = 0.5f * (float)(N - 1);
@@ -408,9 +413,10 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc* const* dptrs, int wit
     block_sum<3>(ps, red);
   }
   if (use_args && blockIdx.x == 0 && threadIdx.x == 0) {
-    const auto d = glb(dptrs[blockIdx.y]);
+    const auto d = glb(dp);
     d->y = a.y[blockIdx.y];
     d->cur = cur;
+    if (use_args == 2) glb(dptrs)[blockIdx.y] = dp;
   }
   if (threadIdx.x == 0) {
     float* out = glb(D.part) + blockIdx.x * PART_STRIDE;
@@ -1377,7 +1383,8 @@ hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const
 }
 
 hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, const float2* const* ys,
-                        const int* curs, hipStream_t st) {
+                        const int* curs, StreamDesc* const* ds, hipStream_t st) {
+  StreamDesc** list = const_cast<StreamDesc**>(dptrs);
   for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
     FrameArgs a{};
     const int n = count - off < FRAME_ARGS_MAX ? count - off : FRAME_ARGS_MAX;
@@ -1385,10 +1392,12 @@ hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi
       for (int i = 0; i < n; ++i) {
         a.y[i] = ys[off + i];
         a.cur[i] = curs[off + i];
+        a.d[i] = ds ? ds[off + i] : nullptr;
       }
+    const int mode = ys ? (ds ? 2 : 1) : 0;
 #define DDH_X(NN)                                                                                  \
-  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, n), dim3(256), 0, st, dptrs + off, \
-                     with_phi, a, ys ? 1 : 0);                                                      \
+  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, n), dim3(256), 0, st, list + off, \
+                     with_phi, a, mode);                                                            \
   break;
     switch (N) {
       case 64: DDH_X(64)

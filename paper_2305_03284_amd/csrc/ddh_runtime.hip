@@ -200,6 +200,22 @@ struct ddh_batch_s {
   bool alive() const { return magic == kAlive; }
 };
 
+// Continuous-batching server: a device list of descriptor pointers, filled per
+// call by the stats kernel from its arguments.
+struct ddh_server_s {
+  uint32_t magic = kAlive;
+  int device = 0;
+  int max = 0;
+  StreamDesc** list = nullptr;  // device, max entries
+  bool bound = false;           // calls are bound to the first call's HIP stream
+  hipStream_t st = nullptr;
+  std::vector<int> order;
+  std::vector<const float2*> ys;
+  std::vector<int> curs;
+  std::vector<StreamDesc*> ds;
+  bool alive() const { return magic == kAlive; }
+};
+
 namespace {
 
 // Enqueue one frame (mode 1: DDH frame with prologue; mode 0: plain EM) for
@@ -207,12 +223,13 @@ namespace {
 // around every launch.
 template <class OnLaunch>
 int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int total, int n_k, int mode,
-                  hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr) {
+                  hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr,
+                  StreamDesc* const* ds = nullptr) {
   hipError_t e;
   for (const Group& g : groups) {
     e = around(KK_STATS, [&] {
       return launch_stats(dptrs + g.off, g.count, g.N, mode, ys ? ys + g.off : nullptr, ys ? curs + g.off : nullptr,
-                          st);
+                          ds ? ds + g.off : nullptr, st);
     });
     if (e != hipSuccess) return hip_fail(e, "launch_stats");
   }
@@ -331,6 +348,40 @@ int ddh_default_params(int N, ddh_params* p) {
   return DDH_OK;
 }
 
+// Device allocation of one stream (one hipMalloc): offsets of its buffers.
+struct StreamLayout {
+  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, total;
+  explicit StreamLayout(int N) {
+    const size_t px = (size_t)N * N;
+    const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    r0 = take(px * 4);
+    r1 = take(px * 4);
+    p0 = take(px * 4);
+    p1 = take(px * 4);
+    T = take(px * 8);
+    U = take(px * 8);
+    bb = take(px * 4);
+    part = take((size_t)nb * PART_STRIDE * 4);
+    scal = take(SC_COUNT * 4);
+    desc = take(sizeof(StreamDesc));
+    dptr = take(sizeof(StreamDesc*));
+    diag = take(kDiagParts * 3 * sizeof(double) + 64);
+    total = off;
+  }
+};
+
+int ddh_stream_bytes(int N, unsigned long long* bytes) {
+  if (!bytes || !valid_N(N)) return DDH_EINVAL;
+  *bytes = StreamLayout(N).total;
+  return DDH_OK;
+}
+
 int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   if (!out) return DDH_EINVAL;
   int rc = validate(p);
@@ -342,22 +393,11 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   rc = ensure_twiddles(dev, &tw_all);
   if (rc != DDH_OK) return rc;
   const int N = p->N;
-  const size_t px = (size_t)N * N;
-  const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
-  // layout
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off = align256(off + bytes);
-    return o;
-  };
-  const size_t o_r0 = take(px * 4), o_r1 = take(px * 4), o_p0 = take(px * 4), o_p1 = take(px * 4);
-  const size_t o_T = take(px * 8), o_U = take(px * 8), o_bb = take(px * 4);
-  const size_t o_part = take((size_t)nb * PART_STRIDE * 4), o_scal = take(SC_COUNT * 4);
-  const size_t o_desc = take(sizeof(StreamDesc)), o_dptr = take(sizeof(StreamDesc*));
-  const size_t o_diag = take(kDiagParts * 3 * sizeof(double) + 64);
+  const StreamLayout lay(N);
+  const size_t o_r0 = lay.r0, o_r1 = lay.r1, o_p0 = lay.p0, o_p1 = lay.p1, o_T = lay.T, o_U = lay.U, o_bb = lay.bb;
+  const size_t o_part = lay.part, o_scal = lay.scal, o_desc = lay.desc, o_dptr = lay.dptr, o_diag = lay.diag;
   char* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, off);
+  hipError_t e = hipMalloc(&mem, lay.total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(stream)");
   ddh_stream_t s = new ddh_stream_s();
   s->prm = *p;
@@ -531,7 +571,7 @@ int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream) {
   if (!y || !U) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const float2* yp = static_cast<const float2*>(y);
-  hipError_t e = launch_stats(s->dptr, 1, s->N, 0, &yp, &s->parity, st);
+  hipError_t e = launch_stats(s->dptr, 1, s->N, 0, &yp, &s->parity, nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "stats");
   e = launch_finalize(s->dptr, 1, 0, st);
   if (e != hipSuccess) return hip_fail(e, "finalize");
@@ -816,6 +856,93 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
   for (ddh_stream_t s : b->streams) {
     s->parity = (s->parity + b->n_k) & 1;
     s->n++;
+  }
+  return DDH_OK;
+}
+
+// ---------------------------------------------------------------- serving
+int ddh_server_create(int max_streams, ddh_server_t* out) {
+  if (!out || max_streams < 1 || max_streams > (1 << 20)) return DDH_EINVAL;
+  int dev = 0;
+  DDH_CHECK(hipGetDevice(&dev));
+  ddh_server_t v = new ddh_server_s();
+  v->device = dev;
+  v->max = max_streams;
+  hipError_t e = hipMalloc(&v->list, sizeof(StreamDesc*) * max_streams);
+  if (e != hipSuccess) {
+    delete v;
+    return hip_fail(e, "hipMalloc(server)");
+  }
+  *out = v;
+  return DDH_OK;
+}
+
+int ddh_server_destroy(ddh_server_t v) {
+  if (!v) return DDH_EINVAL;
+  if (!v->alive()) return DDH_ESTATE;
+  set_device_of(v->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(v->list);
+  v->magic = kDead;
+  delete v;
+  return DDH_OK;
+}
+
+int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream) {
+  if (!v || (count > 0 && (!streams || !y))) return DDH_EINVAL;
+  if (!v->alive()) return DDH_ESTATE;
+  if (count < 0 || count > v->max) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < count; ++i) {
+    int rc = check_stream(streams[i]);
+    if (rc != DDH_OK) return rc;
+    if (streams[i]->device != v->device) return DDH_ESTATE;
+    if (!y[i]) return DDH_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == streams[i]) return DDH_EINVAL;
+  }
+  if (v->bound && st != v->st) return DDH_ESTATE;
+  if (count == 0) return DDH_OK;
+  v->bound = true;
+  v->st = st;
+  // list order: by n_k, then by N (the per-N kernels take contiguous ranges)
+  v->order.resize(count);
+  for (int i = 0; i < count; ++i) v->order[i] = i;
+  std::stable_sort(v->order.begin(), v->order.end(), [&](int a, int c) {
+    if (streams[a]->prm.n_k != streams[c]->prm.n_k) return streams[a]->prm.n_k < streams[c]->prm.n_k;
+    return streams[a]->N < streams[c]->N;
+  });
+  v->ys.resize(count);
+  v->curs.resize(count);
+  v->ds.resize(count);
+  for (int p = 0; p < count; ++p) {
+    const int i = v->order[p];
+    v->ys[p] = static_cast<const float2*>(y[i]);
+    v->curs[p] = streams[i]->parity;
+    v->ds[p] = streams[i]->d;
+  }
+  int p0 = 0;
+  while (p0 < count) {
+    const int n_k = streams[v->order[p0]]->prm.n_k;
+    int p1 = p0;
+    std::vector<Group> groups;
+    while (p1 < count && streams[v->order[p1]]->prm.n_k == n_k) {
+      const int N = streams[v->order[p1]]->N;
+      Group g{N, p1 - p0, 0, tiles_for(N), streams[v->order[p1]]->tw};
+      while (p1 < count && streams[v->order[p1]]->prm.n_k == n_k && streams[v->order[p1]]->N == N) {
+        ++g.count;
+        ++p1;
+      }
+      groups.push_back(g);
+    }
+    int rc = enqueue_frame(v->list + p0, groups, p1 - p0, n_k, 1, st, NoTiming{}, v->ys.data() + p0,
+                           v->curs.data() + p0, v->ds.data() + p0);
+    if (rc != DDH_OK) return rc;
+    p0 = p1;
+  }
+  for (int i = 0; i < count; ++i) {
+    streams[i]->parity = (streams[i]->parity + streams[i]->prm.n_k) & 1;
+    streams[i]->n++;
   }
   return DDH_OK;
 }

@@ -66,6 +66,9 @@ def test_null_handles_are_rejected():
     assert L.ddh_batch_create(None, 0, 0, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_step(None, None, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_destroy(None) == ddh.DDH_EINVAL
+    assert L.ddh_server_destroy(None) == ddh.DDH_EINVAL
+    assert L.ddh_server_step(None, None, None, 0, None) == ddh.DDH_EINVAL
+    assert L.ddh_server_create(0, None) == ddh.DDH_EINVAL
     n = ctypes.c_longlong()
     assert L.ddh_frame_count(None, ctypes.byref(n)) == ddh.DDH_EINVAL
 
@@ -74,3 +77,18 @@ def test_null_handles_are_rejected():
 def test_fft2_validates(N, count, inv):
     one = ctypes.c_void_p(16)
     assert ddh.lib().ddh_fft2(N, count, one, one, one, inv, None) == ddh.DDH_EINVAL
+
+
+def test_stream_bytes_without_a_device():
+    D = ddh
+    b = ctypes.c_ulonglong()
+    sizes = []
+    for N in (64, 128, 256, 512):
+        assert D.lib().ddh_stream_bytes(N, ctypes.byref(b)) == 0
+        # state (2 r + 2 phi), T, U and |b|^2 buffers at least, 256-byte aligned pieces
+        assert b.value >= 36 * N * N and b.value % 256 == 0
+        sizes.append(b.value)
+    assert sizes == sorted(sizes)
+    assert D.lib().ddh_stream_bytes(100, ctypes.byref(b)) == D.DDH_EINVAL
+    assert D.lib().ddh_stream_bytes(64, None) == D.DDH_EINVAL
+    assert D.stream_bytes(256) == sizes[2]
