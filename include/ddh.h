@@ -149,10 +149,10 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
  * per-frame launch sequence in a HIP graph on first use; DDH_BATCH_LANES(n)
  * (n = 1..8) splits the streams into n lanes balanced by pixel count whose
  * launch chains run on n internal HIP streams forked from and joined back
- * into the caller's stream, so that one lane's compute-bound M-step overlaps
- * another lane's memory-bound FFT passes (a graph then has n parallel
- * branches).  All n_k must be equal.  The batch does not own the streams;
- * destroy the batch before its streams. */
+ * into the caller's stream (a graph then has n parallel branches; on the
+ * 64 x N=256 workload two or more lanes measured slower than one).  All n_k
+ * must be equal.  The batch does not own the streams; destroy the batch
+ * before its streams. */
 #define DDH_BATCH_GRAPH 1
 #define DDH_BATCH_LANES(n) (((n) & 0xff) << 8)
 int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);
@@ -169,9 +169,10 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * (on input *n is the capacity of the arrays), the summed milliseconds ms[k]
  * and launch count calls[k] since timing was enabled, and its name to
  * names[k] (static strings).  Kinds: 0 stats, 1 finalize, 2 row-ifft,
- * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame pointers).  The combine
- * of the stats partials runs inside the first row pass of a frame, so kind 1
- * stays at zero launches in a batch step. */
+ * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame start).  The combine of
+ * the stats partials runs inside the first row pass of a frame, and an eager
+ * step passes the frame start to the stats kernel, so kinds 1 and 6 stay at
+ * zero launches in a timed step. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 
