@@ -47,6 +47,9 @@ struct StreamDesc {
   // pupil moments for the plane fit (exact, host-computed):
   // n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with di = i-c, dj = j-c
   double mom[6];
+  // inverse of the symmetric 3x3 moment matrix [[n, Sdi, Sdj], [Sdi, Sdi2, Sdidj],
+  // [Sdj, Sdidj, Sdj2]] as (00, 01, 02, 11, 12, 22); zero if singular
+  double minv[6];
 };
 
 // Launch-site configuration (autotuned per N).

@@ -439,16 +439,26 @@ __device__ __forceinline__ double wave_sum_d(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
+// Lane l < nb of a wave loads stats block l's partials.
 template <class Desc>
-__device__ void combine_stats(const Desc& D, int with_phi, float* out) {
+__device__ __forceinline__ void load_partials(const Desc& D, float (&p)[6]) {
   const int lane = threadIdx.x & 63;
-  const int N = D.N;
-  const int nb = (N * N) / STATS_PIX_PER_BLOCK;
-  double p[6] = {0, 0, 0, 0, 0, 0};
+  const int nb = (D.N * D.N) / STATS_PIX_PER_BLOCK;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) p[q] = 0.f;
   if (lane < nb) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) p[q] = glb(D.part)[lane * PART_STRIDE + q];
   }
+}
+template <class Desc>
+__device__ void combine_partials(const Desc& D, int with_phi, const float (&pf)[6], float* out) {
+  const int lane = threadIdx.x & 63;
+  const int N = D.N;
+  const int nb = (N * N) / STATS_PIX_PER_BLOCK;
+  double p[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) p[q] = pf[q];
   const double mr = wave_sum_d(p[0]) / nb, mi = wave_sum_d(p[1]) / nb;
   const double dr = lane < nb ? p[0] - mr : 0.0, di = lane < nb ? p[1] - mi : 0.0;
   const double m2 = wave_sum_d(p[2]) + (double)STATS_PIX_PER_BLOCK * wave_sum_d(dr * dr + di * di);
@@ -461,19 +471,22 @@ __device__ void combine_stats(const Desc& D, int with_phi, float* out) {
   out[SC_FLAG] = ok ? 0.0f : 1.0f;
   double c0 = 0, c1 = 0, c2 = 0;
   if (with_phi) {
-    // normal equations of the plane c0 + c1 di + c2 dj over the pupil (Cramer)
-    const double* m = D.mom;
-    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
-    const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
-    if (det != 0.0) {
-      c0 = (s0 * (a11 * a22 - a12 * a12) - a01 * (s1 * a22 - a12 * s2) + a02 * (s1 * a12 - a11 * s2)) / det;
-      c1 = (a00 * (s1 * a22 - a12 * s2) - s0 * (a01 * a22 - a12 * a02) + a02 * (a01 * s2 - s1 * a02)) / det;
-      c2 = (a00 * (a11 * s2 - s1 * a12) - a01 * (a01 * s2 - s1 * a02) + s0 * (a01 * a12 - a11 * a02)) / det;
-    }
+    // least-squares plane c0 + c1 di + c2 dj over the pupil: the normal
+    // equations' inverse matrix is precomputed per stream
+    const auto& m = D.minv;
+    c0 = m[0] * s0 + m[1] * s1 + m[2] * s2;
+    c1 = m[1] * s0 + m[3] * s1 + m[4] * s2;
+    c2 = m[2] * s0 + m[4] * s1 + m[5] * s2;
   }
   out[SC_C0] = (float)c0;
   out[SC_C1] = (float)c1;
   out[SC_C2] = (float)c2;
+}
+template <class Desc>
+__device__ void combine_stats(const Desc& D, int with_phi, float* out) {
+  float p[6];
+  load_partials(D, p);
+  combine_partials(D, with_phi, p, out);
 }
 
 // k_finalize: standalone combine (diagnostic path).  grid (streams), block 64
@@ -598,6 +611,32 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
 }
 
 // ---------------------------------------------------------------------------
+// atan2 in (-pi, pi]: reduction to a = min(|x|,|y|)/max(|x|,|y|) in [0, 1],
+// atan(a) = a + a u Q(u), u = a^2, with a degree-7 Q fitted here (Lawson-
+// weighted least squares towards the minimax of the absolute error on
+// [0, 1]; FP32 evaluation error below 7e-8 absolute and 1e-7 relative),
+// then the octant and quadrant reflections.  atan2(0, 0) = 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fatan2(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float u = a * a;
+  float q = 2.622134222e-03f;
+  q = __builtin_fmaf(q, u, -1.513207969e-02f);
+  q = __builtin_fmaf(q, u, 4.112108693e-02f);
+  q = __builtin_fmaf(q, u, -7.366637325e-02f);
+  q = __builtin_fmaf(q, u, 1.057389778e-01f);
+  q = __builtin_fmaf(q, u, -1.418596587e-01f);
+  q = __builtin_fmaf(q, u, 1.999039534e-01f);
+  q = __builtin_fmaf(q, u, -3.333298699e-01f);
+  float r = __builtin_fmaf(a * u, q, a);
+  r = ay > ax ? 1.57079632679489662f - r : r;
+  r = x < 0.0f ? 3.14159265358979324f - r : r;
+  return copysignf(r, y);
+}
+
+// ---------------------------------------------------------------------------
 // k_row2: forward 1-D DFT along rows of U and the 1/N scale give z = F mu.
 // Per pupil pixel, the phase data term -c cos(phi - theta),
 // c = (2/s2)|yhat||z|, theta = arg(yhat conj z), is majorised at
@@ -654,14 +693,15 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
       const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, m, N) : phv[i];
       // w = exp(j p) conj(yhat) z: |w| = |yhat||z| and arg w = p - theta, so
-      // x0 = arg w lies in (-pi, pi] already and c sin(x0) = (2/s2) Im w.
+      // x0 = arg w lies in [-pi, pi] already (kappa is zero at +-pi) and
+      // c sin(x0) = (2/s2) Im w.
       float sn, cs;
       fsincos(p, &sn, &cs);
       const float qr = yh.x * z.x + yh.y * z.y, qi = yh.x * z.y - yh.y * z.x;  // conj(yhat) z
       const float wr = cs * qr - sn * qi, wi = sn * qr + cs * qi;
-      const float x0 = atan2f(wi, wr);
-      const float ka = fabsf(x0) > 1e-3f ? c2s * wi * __builtin_amdgcn_rcpf(x0)
-                                         : c2s * __builtin_amdgcn_sqrtf(wr * wr + wi * wi) * (1.0f - x0 * x0 * (1.0f / 6.0f));
+      const float x0 = fatan2(wi, wr);
+      // kappa = c sinc(x0) = (2/s2) |w| sin(x0)/x0 = (2/s2) Im(w)/x0 (x0 = 0: w real, |w| = Re w)
+      const float ka = x0 != 0.0f ? c2s * wi * __builtin_amdgcn_rcpf(x0) : c2s * wr;
       res = make_float2(ka, p - x0);
       if (mat) pmat[m] = p;  // the colour passes update this copy in place
     }

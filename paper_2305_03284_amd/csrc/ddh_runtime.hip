@@ -452,6 +452,13 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
         m[5] += b * b;
       }
     memcpy(h.mom, m, sizeof m);
+    // symmetric inverse by cofactors (the plane fit's normal equations)
+    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
+    for (int q = 0; q < 6; ++q) h.minv[q] = det != 0.0 ? inv[q] : 0.0;
   }
   s->d = (StreamDesc*)(mem + o_desc);
   s->dptr = (StreamDesc**)(mem + o_dptr);
