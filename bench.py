@@ -56,6 +56,9 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=2000.0, help="aggregate frame arrival rate (Hz)")
     p.add_argument("--serve-frames", type=int, default=40, help="frames per stream")
     p.add_argument("--serve-budget", type=float, default=0.75, help="memory budget as a fraction of all streams' bytes")
+    p.add_argument("--quality", action="store_true", help="instead: Strehl over the frames for N_k in {1,2,4,8} "
+                   "(10 seeds) and over an alpha/lambda grid")
+    p.add_argument("--quality-frames", type=int, default=150)
     return p.parse_args()
 
 
@@ -207,18 +210,108 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def _quality_stream_frames(args):
+    """(frames, truth phases at the checkpoints) of one seeded stream, as numpy."""
+    seed, T, checkpoints = args
+    import ddh_synth as synth
+    sm = synth.config1_stream(N=256, stream_id=seed)
+    return ([sm.frame(n) for n in range(T)], {c: sm.phase(c - 1).astype(np.float32) for c in checkpoints},
+            sm.sigma_w2)
+
+
+def quality_inputs(T, seeds, checkpoints):
+    """Generated in worker processes before this process touches the GPU."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(len(seeds), 10)) as pool:
+        return pool.map(_quality_stream_frames, [(sd, T, checkpoints) for sd in seeds])
+
+
+def quality_checkpoints(T):
+    return sorted({min(T, c) for c in (1, 10, 25, 50, 100, 150, T)})
+
+
+def quality_main(args, pre):
+    """Reconstruction quality on the streaming workload (N = 256, D/r0 = 15,
+    0.5 px/step, SNR 5): peak Strehl of the estimate at checkpoints over
+    --quality-frames frames, (a) for N_k in {1, 2, 4, 8} over 10 seeded streams
+    (quartiles), (b) for an alpha x lambda grid at N_k = 1 over 3 streams
+    (mean at the last frame).  "uncorrected" is the Strehl of phi = 0."""
+    import torch
+    import paper_2305_03284_amd as D
+    import ddh_synth as synth
+    T = args.quality_frames
+    checkpoints = quality_checkpoints(T)
+    gen, t_gen = pre
+    seeds = list(range(len(gen)))
+    frames = [[torch.from_numpy(f).cuda() for f in g[0]] for g in gen]
+    # after c frames the estimate is compared with the truth of frame c - 1
+    truth = {(i, c): torch.from_numpy(g[1][c]).cuda() for i, g in enumerate(gen) for c in checkpoints}
+    sigma_w2 = [g[2] for g in gen]
+    v = synth.DEFAULT_PARAMS
+
+    def params(i, n_k=1, lam=v["lam"], alpha=v["alpha"]):
+        return D.make_params(256, pupil_diameter=256.0, lam=lam, alpha=alpha, n_k=n_k, sigma_w2=sigma_w2[i],
+                             qg_q=v["qg_q"], qg_T=v["qg_T"], qg_sigma=v["qg_sigma"], beta_phi=v["beta_phi"],
+                             r_floor=v["r_floor"])
+
+    def run(cases):
+        """cases: list of (stream index, Params); returns Strehl[case][checkpoint]."""
+        streams = [D.Stream(256, prm) for _, prm in cases]
+        srv = D.Server(len(cases))
+        out = [[] for _ in cases]
+        for n in range(T):
+            srv.step(streams, [frames[i][n] for i, _ in cases])
+            if n + 1 in checkpoints:
+                for c, (i, _) in enumerate(cases):
+                    out[c].append(streams[c].strehl(truth[(i, n + 1)]))
+        srv.close()
+        for s_ in streams:
+            s_.close()
+        return out
+
+    # uncorrected: Strehl of the true phase alone (estimate phi = 0)
+    probe = D.Stream(256, params(0))
+    uncorr = [[probe.strehl(truth[(i, c)]) for c in checkpoints] for i in range(len(seeds))]
+    probe.close()
+    res = {"uncorrected": {"median": [round(float(np.median([u[k] for u in uncorr])), 4) for k in range(len(checkpoints))]}}
+    for n_k in (1, 2, 4, 8):
+        st = np.array(run([(i, params(i, n_k=n_k)) for i in range(len(seeds))]))
+        res[f"N_k={n_k}"] = {q: [round(float(x), 4) for x in np.percentile(st, pq, axis=0)]
+                              for q, pq in (("q25", 25), ("median", 50), ("q75", 75))}
+    grid = {}
+    for alpha in (0.01, 0.025, 0.05, 0.1):
+        cases = [(i, params(i, lam=lam, alpha=alpha)) for lam in (0.2, 0.45, 0.7, 0.9) for i in range(3)]
+        st = np.array(run(cases))[:, -1].reshape(4, 3).mean(axis=1)
+        for lam, val in zip((0.2, 0.45, 0.7, 0.9), st):
+            grid[f"alpha={alpha},lambda={lam}"] = round(float(val), 4)
+    out = {"metric": "peak Strehl of the phase estimate (streaming workload)", "unit": "Strehl", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "N=256, D/r0=15, 0.5 px/step, SNR 5, frames " + str(T), "seeds": len(seeds)},
+           "checkpoints": checkpoints, "strehl": res, "alpha_lambda_grid_last_frame": grid,
+           "input_generation_s": round(t_gen, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); streams are independent, "
               "so a multi-GPU run shards them with no communication", file=sys.stderr)
         sys.exit(2)
+    pre = None
+    if args.quality:  # host-side inputs first, in worker processes, before any GPU call
+        t0 = time.perf_counter()
+        pre = (quality_inputs(args.quality_frames, list(range(10)), quality_checkpoints(args.quality_frames)),
+               time.perf_counter() - t0)
     import torch
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     if args.serve:
         serve_main(args)
+        return
+    if args.quality:
+        quality_main(args, pre)
         return
     import paper_2305_03284_amd as D
     import ddh_synth as synth
