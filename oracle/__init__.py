@@ -14,7 +14,10 @@ Parity status of each function (what pins it):
   qggmrf_rho / qggmrf_weight .. finite differences; majorisation on a grid
   solve_pixel_r ............... brute-force grid minimiser; no-prior limit r=s
   r_m_step / phi_m_step ....... pixel-by-pixel sequential ICD at N=8;
-                                surrogate decrease; beta=0 limit phi=theta
+                                surrogate decrease; beta=0 limit phi=theta;
+                                noise-free frame, w -> 1: the true phase is
+                                a fixed point and theta equals it (sign and
+                                conjugate conventions of A_phi, A_phi^H, theta)
   em / ddh_frame .............. cost_U non-increasing over 200 iterations;
                                 piston invariance; integer-tilt = image shift
   cost_U ...................... dense Gaussian likelihood at N=8, a=1

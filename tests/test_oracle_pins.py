@@ -509,3 +509,31 @@ def test_frames_are_seeded_and_complex64():
     assert y1.dtype == np.complex64
     np.testing.assert_array_equal(y1, y2)
     assert not np.array_equal(st1.frame(4), y1)
+
+
+def test_true_phase_is_a_fixed_point_of_noise_free_phase_step():
+    """Noise-free frame y = a exp(j phi0) F g and a signal variance far above
+    the noise (w -> 1): the E-step returns mu = b, so z = F mu = a exp(-j phi0)
+    yhat on the pupil and theta = arg(yhat conj z) = phi0; without the prior the
+    phase step must leave phi0 unchanged.  A wrong sign of the phase in A_phi,
+    A_phi^H or theta (or a conjugate missing) moves phi0 by 2 phi0 or more."""
+    N = 16
+    rng = np.random.default_rng(5)
+    a = ddh.aperture(N)
+    phi0 = ddh.remove_tiptilt(rng.uniform(-2.5, 2.5, (N, N)), a)
+    g = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2)
+    y = a * np.exp(1j * phi0) * ddh.F(g)
+    yhat = ddh.normalize(y)
+    b = ddh.back_project(yhat, phi0, a)
+    mu, _, _ = ddh.e_step(np.full((N, N), 1e12), b, 1e-9)
+    z = ddh.F(mu)
+    prm = ddh.Params(sigma_w2=1e-9, beta_phi=0.0)
+    phi1 = ddh.phi_m_step(phi0, yhat, z, a, prm)
+    m = a > 0
+    np.testing.assert_allclose(phi1[m], phi0[m], atol=1e-9)
+    # and from a perturbed phase the same data point back at phi0 in one step
+    # (theta does not depend on the phase used in b when w = 1: it is phi0)
+    phi_off = ddh.remove_tiptilt(phi0 + 0.3 * rng.standard_normal((N, N)) * m, a)
+    z_off = ddh.F(ddh.e_step(np.full((N, N), 1e12), ddh.back_project(yhat, phi_off, a), 1e-9)[0])
+    theta = np.angle(yhat * np.conj(z_off))
+    np.testing.assert_allclose(np.angle(np.exp(1j * (theta[m] - phi_off[m]))), 0.0, atol=1e-9)
