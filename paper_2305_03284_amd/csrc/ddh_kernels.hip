@@ -333,6 +333,24 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red /* >= NV*16
 }
 
 // ---------------------------------------------------------------------------
+// Block -> (item, stream) of a (items, streams) grid.  Workgroups are
+// dispatched round-robin over the 8 XCDs; when the streams split evenly, every
+// block of a stream goes to one XCD (streams [x S/8, (x+1) S/8) on XCD x, the
+// same assignment as the M-step's), so that what one kernel of a stream
+// writes, the next reads through the same L2.
+// ---------------------------------------------------------------------------
+struct XcdBlock {
+  int item, strm;
+};
+__device__ __forceinline__ XcdBlock xcd_block() {
+  const int I = gridDim.x, S = gridDim.y;
+  if (S % 8 != 0) return {(int)blockIdx.x, (int)blockIdx.y};
+  const int L = blockIdx.x + blockIdx.y * I;
+  const int k = L / 8;
+  return {k % I, (L % 8) * (S / 8) + k / I};
+}
+
+// ---------------------------------------------------------------------------
 // Frame start arguments: this frame's y and current state buffer per stream
 // of a launch (at most 64 streams per launch).
 // ---------------------------------------------------------------------------
@@ -363,18 +381,19 @@ __global__ void k_begin(StreamDesc* const* dptrs, FrameArgs a, int count) {
 // stream also stores in the device list dptrs for the later kernels.
 template <int N>
 __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi, FrameArgs a, int use_args) {
-  StreamDesc* const dp = use_args == 2 ? a.d[blockIdx.y] : dptrs[blockIdx.y];
+  const XcdBlock xb = xcd_block();
+  StreamDesc* const dp = use_args == 2 ? a.d[xb.strm] : dptrs[xb.strm];
   const auto& D = desc_ref(dp);
   __shared__ float red[6 * 16];
-  const int base = blockIdx.x * STATS_PIX_PER_BLOCK;
+  const int base = xb.item * STATS_PIX_PER_BLOCK;
   constexpr float c = 0.5f * (float)(N - 1);
   float2 v[16];
   float ph[16];
   // frame start: from the arguments (block 0 stores them in the descriptor
   // for the later kernels; no block of this launch reads them there) or from
   // the descriptor
-  const float2* yv = use_args ? glb(a.y[blockIdx.y]) : glb(D.y);
-  const int cur = use_args ? a.cur[blockIdx.y] : D.cur;
+  const float2* yv = use_args ? glb(a.y[xb.strm]) : glb(D.y);
+  const int cur = use_args ? a.cur[xb.strm] : D.cur;
   const float* phi = glb(D.phi[cur]);
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
@@ -412,14 +431,14 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
     }
     block_sum<3>(ps, red);
   }
-  if (use_args && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (use_args && xb.item == 0 && threadIdx.x == 0) {
     const auto d = glb(dp);
-    d->y = a.y[blockIdx.y];
+    d->y = a.y[xb.strm];
     d->cur = cur;
-    if (use_args == 2) glb(dptrs)[blockIdx.y] = dp;
+    if (use_args == 2) glb(dptrs)[xb.strm] = dp;
   }
   if (threadIdx.x == 0) {
-    float* out = glb(D.part) + blockIdx.x * PART_STRIDE;
+    float* out = glb(D.part) + xb.item * PART_STRIDE;
     out[0] = mr;
     out[1] = mi;
     out[2] = m2[0];
@@ -507,9 +526,10 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
   __shared__ float2 s_tw[N];
   __shared__ float scs[SC_COUNT];
-  const auto& D = desc_ref(dptrs[blockIdx.y]);
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
-  const int row = blockIdx.x * LPW + line;
+  const int row = xb.item * LPW + line;
   const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
   const float2* y = glb(D.y) + row * N;
   // global reads first (they depend on nothing computed here): the row of y
@@ -529,7 +549,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
     // itself (identical arithmetic in all blocks); block 0 publishes them
     if (threadIdx.x < 64) combine_stats(D, with_phi, scs);
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) glb(D.scal)[threadIdx.x] = scs[threadIdx.x];
+    if (xb.item == 0 && threadIdx.x < SC_COUNT) glb(D.scal)[threadIdx.x] = scs[threadIdx.x];
 #pragma unroll
     for (int q = 0; q < SC_COUNT; ++q) sc[q] = scs[q];
   } else {
@@ -574,9 +594,10 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
   constexpr int E = Plan<N>::E;
   __shared__ float2 lds[N * ColLds<W>::STRIDE];
   __shared__ float2 s_tw[N];
-  const auto& D = desc_ref(dptrs[blockIdx.y]);
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
   const int w = threadIdx.x % W, t = threadIdx.x / W;
-  const int col = blockIdx.x * W + w;
+  const int col = xb.item * W + w;
   float2 v[E];
   float rpv[E];
   const float* rin = glb(D.r[(D.cur + k) & 1]);
@@ -649,10 +670,11 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
   __shared__ float2 s_tw[N];
-  const auto& D = desc_ref(dptrs[blockIdx.y]);
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
   const float* sc = glb(D.scal);
   const int line = threadIdx.x / T, t = threadIdx.x - line * T;
-  const int row = blockIdx.x * LPW + line;
+  const int row = xb.item * LPW + line;
   for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
   float2 v[E];
   const float2* u = glb(D.U) + row * N;
