@@ -203,6 +203,34 @@ int ddh_server_destroy(ddh_server_t s);
 int ddh_server_step(ddh_server_t s, const ddh_stream_t* streams, const void* const* y, int count,
                     void* hip_stream);
 
+/* -------------------------------------------------------- differentiation */
+
+/* Gradient of K unrolled DDH frames.  Starting from r = 0 and phi = phi0, the
+ * frames y[0..K-1] (host array of K device pointers, N*N complex64 each) are
+ * processed as by ddh_step with n_k = 1; the loss is the piston-removed RMS
+ * difference over the pupil between the last phase and phi_true (device,
+ * N*N floats).  The adjoint of every step is hand-written: the colour passes
+ * are reversed pass by pass, each reflectance update through the implicit
+ * derivative of its cubic root, the phase data term through its arctangent
+ * and sinc, the E-step, Eq. (3), both DFTs and the tip/tilt removal.  Writes
+ * d loss / d phi0 to d_phi0 (device, N*N floats) and the loss and its
+ * derivatives with respect to sigma_w = sqrt(sigma_w2), the QGGMRF scale
+ * qg_sigma (prior weight 1/qg_sigma^2 and threshold qg_T qg_sigma) and
+ * beta_phi to *out (host).  Only every ckpt-th state is kept during the
+ * forward; the backward recomputes each segment of ckpt frames from it.
+ * Points where the map is not differentiable take the derivative of the
+ * branch the forward took (floors, the root choice, the phase wrap); the
+ * QGGMRF weight's unbounded derivative at zero difference is taken as zero.
+ * Parameters as for ddh_init_stream, with n_k = 1 and qg_p = 2 (DDH_EINVAL
+ * otherwise).  Allocates its workspace, synchronises hip_stream.  DDH_EDATA
+ * if a frame cannot be normalised or the loss is zero. */
+typedef struct {
+  double loss;
+  double d_sigma_w, d_sigma_r, d_beta;
+} ddh_grad_out;
+int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const float* phi0, const float* phi_true,
+                      int ckpt, float* d_phi0, ddh_grad_out* out, void* hip_stream);
+
 /* ---------------------------------------------------------- FFT (a3, a6) */
 
 /* Batched unitary 2D DFT of `count` N x N complex64 images (device pointers,

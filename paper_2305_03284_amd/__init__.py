@@ -34,6 +34,12 @@ class Params(ctypes.Structure):
                 ("qg_sigma", ctypes.c_float), ("beta_phi", ctypes.c_float), ("r_floor", ctypes.c_float)]
 
 
+class GradOut(ctypes.Structure):
+    """ddh_grad_out: loss and its derivatives w.r.t. sigma_w, qg_sigma, beta_phi."""
+    _fields_ = [("loss", ctypes.c_double), ("d_sigma_w", ctypes.c_double), ("d_sigma_r", ctypes.c_double),
+                ("d_beta", ctypes.c_double)]
+
+
 SIGNATURES = {
     "ddh_default_params": (_c_int, [_c_int, ctypes.POINTER(Params)]),
     "ddh_init_stream": (_c_int, [ctypes.POINTER(Params), _c_void_p, ctypes.POINTER(_c_void_p)]),
@@ -59,6 +65,8 @@ SIGNATURES = {
     "ddh_server_destroy": (_c_int, [_c_void_p]),
     "ddh_server_step": (_c_int, [_c_void_p, ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int,
                                  _c_void_p]),
+    "ddh_unrolled_grad": (_c_int, [ctypes.POINTER(Params), _c_int, ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p,
+                                   _c_int, _c_void_p, ctypes.POINTER(GradOut), _c_void_p]),
     "ddh_fft2": (_c_int, [_c_int, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p]),
     "ddh_set_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
     "ddh_get_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
@@ -320,6 +328,57 @@ class Server:
             pass
 
 
+def unrolled_grad(params: Params, frames, phi0, phi_true, ckpt: int = 2):
+    """Loss of len(frames) unrolled DDH frames from r = 0, phi = phi0 (the
+    piston-removed RMS phase error against phi_true after the last frame)
+    and its gradient: (loss, d/dphi0 tensor, d/dsigma_w, d/dqg_sigma,
+    d/dbeta_phi), by the hand-written adjoint (ddh_unrolled_grad)."""
+    torch = _torch()
+    N = params.N
+    for y in frames:
+        _check_frame(y, N)
+    for x in (phi0, phi_true):
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and tuple(x.shape) == (N, N)):
+            raise ValueError("phi0 and phi_true must be contiguous float32 CUDA tensors of shape (N, N)")
+    ys = (ctypes.c_void_p * len(frames))(*[y.data_ptr() for y in frames])
+    g = torch.empty((N, N), dtype=torch.float32, device=phi0.device)
+    out = GradOut()
+    _check(lib().ddh_unrolled_grad(ctypes.byref(params), len(frames), ys, ctypes.c_void_p(phi0.data_ptr()),
+                                   ctypes.c_void_p(phi_true.data_ptr()), int(ckpt), ctypes.c_void_p(g.data_ptr()),
+                                   ctypes.byref(out), _stream_ptr()), "ddh_unrolled_grad")
+    return out.loss, g, out.d_sigma_w, out.d_sigma_r, out.d_beta
+
+
+def unrolled_loss_fn():
+    """torch.autograd.Function over unrolled_grad: forward(phi0, sigma_w,
+    sigma_r, beta, frames, phi_true, base_params, ckpt) -> loss; backward
+    returns the hand-written adjoint's gradients for phi0, sigma_w, sigma_r
+    and beta."""
+    torch = _torch()
+
+    class UnrolledEM(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, phi0, sigma_w, sigma_r, beta, frames, phi_true, base, ckpt=2):
+            prm = Params.from_buffer_copy(base)
+            prm.sigma_w2 = float(sigma_w) ** 2
+            prm.qg_sigma = float(sigma_r)
+            prm.beta_phi = float(beta)
+            prm.n_k = 1
+            L, g, gw, gr, gb = unrolled_grad(prm, frames, phi0.detach().contiguous(), phi_true, ckpt)
+            ctx.save_for_backward(g)
+            ctx.scal = (gw, gr, gb)
+            return torch.tensor(L, dtype=torch.float64, device=phi0.device)
+
+        @staticmethod
+        def backward(ctx, gL):
+            (g,) = ctx.saved_tensors
+            gw, gr, gb = ctx.scal
+            s = gL.to(torch.float64)
+            return ((s * g.double()).to(g.dtype), s * gw, s * gr, s * gb, None, None, None, None)
+
+    return UnrolledEM
+
+
 def fft2(x, inverse: bool = False):
     """Batched unitary 2-D DFT of a contiguous complex64 CUDA tensor (..., N, N)."""
     torch = _torch()
@@ -355,5 +414,5 @@ def autotune(N: int, count: int):
     return tuple(cfg), tuple(us)
 
 
-__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

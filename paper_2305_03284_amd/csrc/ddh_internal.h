@@ -112,4 +112,42 @@ hipError_t launch_synth_frames(float2* y, long long n, unsigned int seed, hipStr
 hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st);
 hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st);
 
+// --- unrolled frames with a hand-written adjoint (ddh_kernels.hip) ---------
+// frame scalars: normalisation and the tip/tilt plane (host-combined FP64 sums)
+struct GradScal {
+  float mu_re, mu_im, scale, c0, c1, c2;
+};
+// constants of the differentiated stream (sig_r: QGGMRF scale, for its gradient)
+struct GradPrm {
+  int N;
+  float d2, lam, alpha, fl, s2, inv_sp, lc, pmq, qop, beta, sig_r;
+};
+// one frame's inputs, intermediates and outputs (device arrays of N*N)
+struct GradFwd {
+  const float2* y;
+  const float* phi_in;
+  const float* r_in;
+  GradPrm prm;
+  GradScal scal;
+  float2 *yh, *v, *b, *mu, *z, *work;
+  float *phip, *s, *kap, *tth;
+  float* rs[5];  // r before colour pass c (rs[0] = Eq. (3) value), rs[4] = output
+  float* ps[5];  // phi after colour pass c-1 (ps[4] = output); pass 0 reads phip
+  const float2* tw;
+};
+// adjoint work arrays (device, N*N); gs2, gsr, gbeta accumulate per pixel
+struct GradBwd {
+  float *rbar, *pbar, *pb2, *em, *kbar, *tbar, *sbar, *Abar, *Bbar;
+  float2 *zbar, *mubar, *bbar, *vbar;
+  float *gs2, *gsr, *gbeta;
+};
+hipError_t g_launch_ysum(const float2* y, int N, double* part, hipStream_t st);
+hipError_t g_launch_psum(const float* f, int N, float d2, double* part, hipStream_t st);
+hipError_t g_launch_dsum(const float* phi, const float* ptrue, int N, float d2, double* part, hipStream_t st);
+hipError_t g_launch_forward(const GradFwd& a, hipStream_t st);
+hipError_t g_launch_loss_bar(const float* phi, const float* ptrue, const GradFwd& a, float dmean, float inv_nL,
+                             float* pbar, hipStream_t st);
+hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, hipStream_t st);
+hipError_t g_launch_plane_bar(const float* pb2, const GradFwd& a, const float* coef, float* pbar, hipStream_t st);
+
 }  // namespace ddh

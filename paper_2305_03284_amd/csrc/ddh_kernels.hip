@@ -1653,4 +1653,487 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st
   return hipGetLastError();
 }
 
+
+// ===========================================================================
+// Unrolled frames with a hand-written adjoint (gradient of a loss on the last
+// frame's phase with respect to the initial phase, sigma_w, the QGGMRF scale
+// sigma_r and the phase-prior weight beta).  Plain whole-image kernels, one
+// thread per pixel, no fusion: they keep every intermediate the adjoint needs.
+// The forward uses the same per-pixel helpers as the fast path (the colour
+// passes are those of k_mpass).  Arrays are N x N, row-major.
+// ===========================================================================
+
+
+__device__ __forceinline__ bool g_pix(int& i, int& j, int N) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  i = p / N;
+  j = p - i * N;
+  return p < N * N;
+}
+__device__ __forceinline__ void g_block_sums(double (&x)[3], double* part) {
+  __shared__ double red[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = wave_sum_d(x[k]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k][wv] = x[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[blockIdx.x * 3 + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+}
+
+// sums of Re y, Im y, |y|^2 (FP64 block partials)
+__global__ __launch_bounds__(256) void k_g_ysum(const float2* y, int N, double* part) {
+  int i, j;
+  double x[3] = {0, 0, 0};
+  if (g_pix(i, j, N)) {
+    const float2 v = y[i * N + j];
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = (double)v.x * v.x + (double)v.y * v.y;
+  }
+  g_block_sums(x, part);
+}
+// plane-fit sums over the pupil of f: sum f, sum (i-c) f, sum (j-c) f
+__global__ __launch_bounds__(256) void k_g_psum(const float* f, int N, float d2, double* part) {
+  int i, j;
+  double x[3] = {0, 0, 0};
+  if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
+    const double c = 0.5 * (N - 1), v = f[i * N + j];
+    x[0] = v;
+    x[1] = (i - c) * v;
+    x[2] = (j - c) * v;
+  }
+  g_block_sums(x, part);
+}
+// piston-removed phase error sums over the pupil: sum d, sum d^2, d = phi - phi_true
+__global__ __launch_bounds__(256) void k_g_dsum(const float* phi, const float* ptrue, int N, float d2, double* part) {
+  int i, j;
+  double x[3] = {0, 0, 0};
+  if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
+    const double d = (double)phi[i * N + j] - ptrue[i * N + j];
+    x[0] = d;
+    x[1] = d * d;
+    x[2] = 1.0;
+  }
+  g_block_sums(x, part);
+}
+
+// frame prologue: yhat, phi' (plane removed, zero off the pupil), v = a exp(-j phi') yhat
+__global__ __launch_bounds__(256) void k_g_prologue(const float2* y, const float* phi, GradPrm P, GradScal S,
+                                                    float2* yh, float* phip, float2* v) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  const float2 yy = y[p];
+  const float2 h = make_float2((yy.x - S.mu_re) * S.scale, (yy.y - S.mu_im) * S.scale);
+  yh[p] = h;
+  float ph = 0.f;
+  float2 vv = make_float2(0.f, 0.f);
+  if (in_pupil(i, j, P.N, P.d2)) {
+    ph = phi[p] - plane_val(S.c0, S.c1, S.c2, i, j, P.N);
+    float sn, cs;
+    fsincos(ph, &sn, &cs);
+    vv = cmul(h, make_float2(cs, -sn));
+  }
+  phip[p] = ph;
+  v[p] = vv;
+}
+// Eq. (3) and the E-step: r0, mu (into mu), s
+__global__ __launch_bounds__(256) void k_g_estep(const float* rprev, const float2* b, GradPrm P, float* r0, float2* mu,
+                                                 float* s) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  const float2 bv = b[p];
+  const float bb = bv.x * bv.x + bv.y * bv.y;
+  const float r = rinit_of(rprev[p], bb, P.lam, P.alpha, P.fl);
+  const float w = wiener_of(r, P.s2);
+  r0[p] = r;
+  mu[p] = make_float2(w * bv.x, w * bv.y);
+  s[p] = second_moment(w, bb, P.s2);
+}
+// phase data term: kappa, theta~ on the pupil (as the fast path's second row pass)
+__device__ __forceinline__ void g_data_u(float2 h, float ph, float2 z, float& ur, float& ui) {
+  float sn, cs;
+  fsincos(ph, &sn, &cs);
+  const float qr = h.x * z.x + h.y * z.y, qi = h.x * z.y - h.y * z.x;  // conj(yhat) z
+  ur = cs * qr - sn * qi;
+  ui = sn * qr + cs * qi;
+}
+__global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* phip, const float2* z, GradPrm P,
+                                                float* kap, float* tth) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  float ka = 0.f, tt = 0.f;
+  if (in_pupil(i, j, P.N, P.d2)) {
+    float ur, ui;
+    g_data_u(yh[p], phip[p], z[p], ur, ui);
+    const float x0 = fatan2(ui, ur);
+    const float c2s = 2.0f / P.s2;
+    ka = x0 != 0.0f ? c2s * ui * __builtin_amdgcn_rcpf(x0) : c2s * ur;
+    tt = phip[p] - x0;
+  }
+  kap[p] = ka;
+  tth[p] = tt;
+}
+// colour pass C of the r M-step, out of place (rin -> rout)
+template <int C>
+__global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* s, GradPrm P, float* rout) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  if ((i & 1) + 2 * (j & 1) != C) {
+    rout[p] = rin[p];
+    return;
+  }
+  const bool up = i > 0, dn = i < N - 1, lf = j > 0, rt = j < N - 1;
+  float rq[8];
+  rq[0] = up ? rin[p - N] : 0.f;
+  rq[1] = dn ? rin[p + N] : 0.f;
+  rq[2] = lf ? rin[p - 1] : 0.f;
+  rq[3] = rt ? rin[p + 1] : 0.f;
+  rq[4] = (up && lf) ? rin[p - N - 1] : 0.f;
+  rq[5] = (up && rt) ? rin[p - N + 1] : 0.f;
+  rq[6] = (dn && lf) ? rin[p + N - 1] : 0.f;
+  rq[7] = (dn && rt) ? rin[p + N + 1] : 0.f;
+  rout[p] = r_pixel<true>(rin[p], s[p], rq, nb_mask(i, j, N), P.inv_sp, P.lc, P.pmq, P.qop, P.fl);
+}
+// colour pass C of the phi M-step, out of place
+template <int C>
+__global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* kap, const float* tth, GradPrm P,
+                                                 float* pout) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) {
+    pout[p] = pin[p];
+    return;
+  }
+  const bool up = i > 0, dn = i < N - 1, lf = j > 0, rt = j < N - 1;
+  float pq[8];
+  pq[0] = up ? pin[p - N] : 0.f;
+  pq[1] = dn ? pin[p + N] : 0.f;
+  pq[2] = lf ? pin[p - 1] : 0.f;
+  pq[3] = rt ? pin[p + 1] : 0.f;
+  pq[4] = (up && lf) ? pin[p - N - 1] : 0.f;
+  pq[5] = (up && rt) ? pin[p - N + 1] : 0.f;
+  pq[6] = (dn && lf) ? pin[p + N - 1] : 0.f;
+  pq[7] = (dn && rt) ? pin[p + N + 1] : 0.f;
+  pout[p] = phi_pixel(pq, pupil_weight_of(pupil_nbr_12(i, j, N, P.d2)), kap[p], tth[p], 2.0f * P.beta, pin[p]);
+}
+
+// ---------------------------------------------------------------- adjoint
+// loss: L = sqrt(mean(d - mean d)^2) over the pupil; dL/dphi = (d - mean d)/(n L)
+__global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const float* ptrue, GradPrm P, float dmean,
+                                                    float inv_nL, float* pbar) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  pbar[p] = in_pupil(i, j, P.N, P.d2) ? (phi[p] - ptrue[p] - dmean) * inv_nL : 0.f;
+}
+// phi pass C reversed, part a: the colour-C pupil pixels hand their adjoint to
+// kappa, theta~, beta and (as em = pbar 2 beta / den) to their neighbours
+template <int C>
+__global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float* pout, const float* kap,
+                                                   const float* tth, GradPrm P, float* pbar, float* em, float* kbar,
+                                                   float* tbar, float* gbeta) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  em[p] = 0.f;
+  if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) return;
+  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+  float Ph = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ii = i + nb[e][0], jj = j + nb[e][1];
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N) Ph += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * pin[ii * N + jj];
+  }
+  const float Pw = pupil_weight_of(pupil_nbr_12(i, j, N, P.d2));
+  const float ka = kap[p], beta2 = 2.0f * P.beta;
+  const float den = ka + beta2 * Pw;
+  if (!(den > 0.0f)) return;  // the pixel kept its value: its adjoint passes through
+  const float g = pbar[p], inv = 1.0f / den, out = pout[p];
+  em[p] = g * beta2 * inv;
+  kbar[p] += g * (tth[p] - out) * inv;
+  tbar[p] += g * ka * inv;
+  gbeta[p] += g * 2.0f * (Ph - Pw * out) * inv;
+  pbar[p] = 0.f;
+}
+// part b: pupil pixels gather em of their colour-C pupil neighbours
+__global__ __launch_bounds__(256) void k_g_pback_b(const float* em, GradPrm P, float* pbar) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  if (!in_pupil(i, j, N, P.d2)) return;
+  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+  float acc = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ii = i + nb[e][0], jj = j + nb[e][1];
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N) acc += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * em[ii * N + jj];
+  }
+  pbar[p] += acc;
+}
+// data term reversed: (kbar, tbar) -> phi' (pb2 += ...), z (zbar), s2
+__global__ __launch_bounds__(256) void k_g_data_bar(const float2* yh, const float* phip, const float2* z,
+                                                    const float* kap, const float* kbar, const float* tbar, GradPrm P,
+                                                    float* pb2, float2* zbar, float* gs2) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  zbar[p] = make_float2(0.f, 0.f);
+  if (!in_pupil(i, j, P.N, P.d2)) return;
+  float ur, ui;
+  g_data_u(yh[p], phip[p], z[p], ur, ui);
+  const float x0 = fatan2(ui, ur);
+  const float mag = sqrtf(ur * ur + ui * ui);
+  const float c2s = 2.0f / P.s2;
+  float sc, dsc;  // sinc(x0) and its derivative
+  if (fabsf(x0) > 1e-3f) {
+    float sn, cs;
+    sincosf(x0, &sn, &cs);
+    sc = sn / x0;
+    dsc = (x0 * cs - sn) / (x0 * x0);
+  } else {
+    sc = 1.0f - x0 * x0 * (1.0f / 6.0f);
+    dsc = -x0 * (1.0f / 3.0f);
+  }
+  const float kb = kbar[p], tb = tbar[p];
+  const float xb = kb * c2s * mag * dsc - tb;  // adjoint of x0
+  const float mb = kb * c2s * sc;              // adjoint of |u|
+  gs2[p] += -kb * kap[p] / P.s2;
+  pb2[p] += tb + xb;
+  // u = gz z with gz = exp(j phi') conj(yhat): dx0 = Im(gz dz / u), d|u| = Re(conj(u) gz dz)/|u|
+  if (mag > 0.0f) {
+    float sn, cs;
+    fsincos(phip[p], &sn, &cs);
+    const float2 h = yh[p];
+    const float2 gz = make_float2(cs * h.x + sn * h.y, sn * h.x - cs * h.y);  // exp(j phi') conj(yhat)
+    const float inv2 = 1.0f / (mag * mag);
+    // j conj(gz / u) = j conj(gz) u / |u|^2 ; u conj(gz) / |u|
+    const float2 cgzu = make_float2(gz.x * ur + gz.y * ui, gz.x * ui - gz.y * ur);  // conj(gz) u
+    zbar[p] = make_float2(xb * (-cgzu.y) * inv2 + mb * cgzu.x / mag, xb * cgzu.x * inv2 + mb * cgzu.y / mag);
+  }
+}
+// QGGMRF edge shape and its derivative in d (zero at d = 0, where it is unbounded)
+__device__ __forceinline__ void g_shape(float d, const GradPrm& P, float& sh, float& dsh, float& dsh_dsig) {
+  const float ad = fabsf(d);
+  const float v = P.pmq > 0.0f ? (ad > 0.0f ? exp2f(__builtin_fmaf(P.pmq, log2f(ad), P.lc)) : 0.0f) : 1.0f;
+  const float u = 1.0f / (1.0f + v);
+  sh = u * __builtin_fmaf(1.0f - P.qop, u, P.qop);
+  const float dsh_dv = (P.qop - 2.0f - P.qop * v) * u * u * u;
+  dsh = (P.pmq > 0.0f && ad > 0.0f) ? dsh_dv * P.pmq * v / d : 0.0f;
+  dsh_dsig = P.pmq > 0.0f ? dsh_dv * (-P.pmq * v / P.sig_r) : 0.0f;
+}
+// r pass C reversed, part a: colour-C pixels turn their adjoint into (Abar,
+// Bbar, sbar), their own old value's adjoint and the sigma_r gradient
+template <int C>
+__global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float* rout, const float* s, GradPrm P,
+                                                   float* rbar, float* sbar, float* Abar, float* Bbar, float* gsr) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  Abar[p] = 0.f;
+  Bbar[p] = 0.f;
+  if ((i & 1) + 2 * (j & 1) != C) return;
+  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+  const float ri = rin[p];
+  float A = 0.f, B = 0.f;
+  float sh[8], dsh[8], dss[8], rq[8], W[8];
+  bool ok[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ii = i + nb[e][0], jj = j + nb[e][1];
+    ok[e] = ii >= 0 && ii < N && jj >= 0 && jj < N;
+    rq[e] = ok[e] ? rin[ii * N + jj] : 0.f;
+    W[e] = ok[e] ? P.inv_sp * (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) : 0.f;
+    g_shape(ri - rq[e], P, sh[e], dsh[e], dss[e]);
+    A += W[e] * sh[e];
+    B += W[e] * sh[e] * rq[e];
+  }
+  const float g = rbar[p];
+  rbar[p] = 0.f;
+  const float rho = rout[p];
+  if (!(rho > P.fl)) return;  // floored: no dependence on the inputs
+  if (!(A > 0.0f)) {          // no prior: rho = s
+    sbar[p] += g;
+    return;
+  }
+  const float fp = (3.0f * A * rho - 2.0f * B) * rho + 1.0f;
+  if (fp == 0.0f) return;
+  const float inv = 1.0f / fp;
+  const float ab = -g * rho * rho * rho * inv, bb = g * rho * rho * inv;
+  sbar[p] += g * inv;
+  Abar[p] = ab;
+  Bbar[p] = bb;
+  float own = 0.f, gs = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    if (!ok[e]) continue;
+    const float shb = W[e] * (ab + bb * rq[e]);  // adjoint of sh_e
+    own += shb * dsh[e];
+    // d(W sh)/d sigma_r = -2 W sh / sigma_r + W dsh/dsigma
+    gs += (ab + bb * rq[e]) * (-2.0f * W[e] * sh[e] / P.sig_r + W[e] * dss[e]);
+  }
+  rbar[p] = own;
+  gsr[p] += gs;
+}
+// part b: every pixel not of colour C gathers from its colour-C neighbours
+template <int C>
+__global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float* Abar, const float* Bbar, GradPrm P,
+                                                   float* rbar) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int N = P.N, p = i * N + j;
+  if ((i & 1) + 2 * (j & 1) == C) return;
+  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+  const float rj = rin[p];
+  float acc = 0.f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ii = i + nb[e][0], jj = j + nb[e][1];
+    if (!(ii >= 0 && ii < N && jj >= 0 && jj < N)) continue;
+    const int q = ii * N + jj;
+    if ((ii & 1) + 2 * (jj & 1) != C) continue;
+    const float ab = Abar[q], bb = Bbar[q];
+    if (ab == 0.0f && bb == 0.0f) continue;
+    float sh, dsh, dss;
+    g_shape(rin[q] - rj, P, sh, dsh, dss);
+    const float W = P.inv_sp * (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f);
+    acc += bb * W * sh - W * (ab + bb * rj) * dsh;
+  }
+  rbar[p] += acc;
+}
+// E-step and Eq. (3) reversed: (mubar, sbar, r0bar) -> bbar, rbar of the previous state, s2
+__global__ __launch_bounds__(256) void k_g_estep_bar(const float* rprev, const float2* b, const float* r0,
+                                                     const float2* mubar, const float* sbar, GradPrm P, float* rbar,
+                                                     float2* bbar, float* gs2) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  const float2 bv = b[p], mb = mubar[p];
+  const float bb = bv.x * bv.x + bv.y * bv.y;
+  const float r = r0[p], den = r + P.s2, w = r / den;
+  const float sb = sbar[p];
+  const float wb = (mb.x * bv.x + mb.y * bv.y) + sb * (P.s2 + 2.0f * w * bb);
+  float2 gb = make_float2(w * mb.x + 2.0f * sb * w * w * bv.x, w * mb.y + 2.0f * sb * w * w * bv.y);
+  float g2 = sb * w - wb * r / (den * den);
+  const float r0b = rbar[p] + wb * P.s2 / (den * den);
+  const float x = (1.0f - P.lam) * rprev[p] + P.lam * P.alpha * bb;
+  float rp = 0.f;
+  if (x > P.fl) {
+    rp = (1.0f - P.lam) * r0b;
+    gb.x += 2.0f * P.lam * P.alpha * r0b * bv.x;
+    gb.y += 2.0f * P.lam * P.alpha * r0b * bv.y;
+  }
+  rbar[p] = rp;
+  bbar[p] = gb;
+  gs2[p] += g2;
+}
+// back-projection reversed: phi' adjoint += Im(conj(vbar) v), v = a exp(-j phi') yhat
+__global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const float2* yh, const float* phip, GradPrm P,
+                                                  float* pb2) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  if (!in_pupil(i, j, P.N, P.d2)) return;
+  float sn, cs;
+  fsincos(phip[p], &sn, &cs);
+  const float2 v = cmul(yh[p], make_float2(cs, -sn)), vb = vbar[p];
+  pb2[p] += vb.x * v.y - vb.y * v.x;
+}
+// tip/tilt removal reversed: pbar = pupil ? pb2 - plane(pb2) : 0
+__global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, GradPrm P, GradScal S, float* pbar) {
+  int i, j;
+  if (!g_pix(i, j, P.N)) return;
+  const int p = i * P.N + j;
+  pbar[p] = in_pupil(i, j, P.N, P.d2) ? pb2[p] - plane_val(S.c0, S.c1, S.c2, i, j, P.N) : 0.f;
+}
+
+#define DDH_G_GRID(N) dim3(((N) * (N) + 255) / 256), dim3(256), 0, st
+hipError_t g_launch_ysum(const float2* y, int N, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_g_ysum, DDH_G_GRID(N), y, N, part);
+  return hipGetLastError();
+}
+hipError_t g_launch_psum(const float* f, int N, float d2, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N), f, N, d2, part);
+  return hipGetLastError();
+}
+hipError_t g_launch_dsum(const float* phi, const float* ptrue, int N, float d2, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_g_dsum, DDH_G_GRID(N), phi, ptrue, N, d2, part);
+  return hipGetLastError();
+}
+hipError_t g_launch_forward(const GradFwd& a, hipStream_t st) {
+  const GradPrm P = a.prm;
+  const GradScal S = a.scal;
+  const int N = P.N;
+  hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N), a.y, a.phi_in, P, S, a.yh, a.phip, a.v);
+  hipError_t e = launch_fft2(N, 1, a.v, a.b, a.work, a.tw, 1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_g_estep, DDH_G_GRID(N), a.r_in, a.b, P, a.rs[0], a.mu, a.s);
+  e = launch_fft2(N, 1, a.mu, a.z, a.work, a.tw, 0, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N), a.yh, a.phip, a.z, P, a.kap, a.tth);
+  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_GRID(N), a.rs[0], a.s, P, a.rs[1]);
+  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_GRID(N), a.rs[1], a.s, P, a.rs[2]);
+  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_GRID(N), a.rs[2], a.s, P, a.rs[3]);
+  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_GRID(N), a.rs[3], a.s, P, a.rs[4]);
+  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_GRID(N), a.phip, a.kap, a.tth, P, a.ps[1]);
+  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_GRID(N), a.ps[1], a.kap, a.tth, P, a.ps[2]);
+  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_GRID(N), a.ps[2], a.kap, a.tth, P, a.ps[3]);
+  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_GRID(N), a.ps[3], a.kap, a.tth, P, a.ps[4]);
+  return hipGetLastError();
+}
+hipError_t g_launch_loss_bar(const float* phi, const float* ptrue, const GradFwd& a, float dmean, float inv_nL,
+                             float* pbar, hipStream_t st) {
+  const GradPrm P = a.prm;
+  hipLaunchKernelGGL(k_g_loss_bar, DDH_G_GRID(P.N), phi, ptrue, P, dmean, inv_nL, pbar);
+  return hipGetLastError();
+}
+// frame reversed up to the tip/tilt adjoint sums: leaves rbar = adjoint of the
+// frame's input r, pb2 = adjoint of phi' (before the plane projection)
+hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, hipStream_t st) {
+  const GradPrm P = a.prm;
+  const int N = P.N;
+  // phi sweep reversed (ps[c] = input of pass c, ps[0] = phi')
+  const float* ps0 = a.phip;
+#define DDH_PB(C)                                                                                                  \
+  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_GRID(N), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, P, g.pbar, \
+                     g.em, g.kbar, g.tbar, g.gbeta);                                                              \
+  hipLaunchKernelGGL(k_g_pback_b, DDH_G_GRID(N), g.em, P, g.pbar);
+  DDH_PB(3) DDH_PB(2) DDH_PB(1) DDH_PB(0)
+#undef DDH_PB
+  hipError_t e = launch_copy(g.pb2, g.pbar, (long long)N * N, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, P, g.pb2, g.zbar, g.gs2);
+  // r sweep reversed (rs[c] = input of pass c)
+#define DDH_RB(C)                                                                                             \
+  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_GRID(N), a.rs[C], a.rs[C + 1], a.s, P, g.rbar, g.sbar, g.Abar, g.Bbar, \
+                     g.gsr);                                                                                 \
+  hipLaunchKernelGGL(k_g_rback_b<C>, DDH_G_GRID(N), a.rs[C], g.Abar, g.Bbar, P, g.rbar);
+  DDH_RB(3) DDH_RB(2) DDH_RB(1) DDH_RB(0)
+#undef DDH_RB
+  // z = F mu  ->  mubar = F^H zbar
+  e = launch_fft2(N, 1, g.zbar, g.mubar, a.work, a.tw, 1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_g_estep_bar, DDH_G_GRID(N), a.r_in, a.b, a.rs[0], g.mubar, g.sbar, P, g.rbar, g.bbar, g.gs2);
+  // b = F^H v  ->  vbar = F bbar
+  e = launch_fft2(N, 1, g.bbar, g.vbar, a.work, a.tw, 0, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_g_bp_bar, DDH_G_GRID(N), g.vbar, a.yh, a.phip, P, g.pb2);
+  return hipGetLastError();
+}
+hipError_t g_launch_plane_bar(const float* pb2, const GradFwd& a, const float* coef, float* pbar, hipStream_t st) {
+  const GradPrm P = a.prm;
+  GradScal S{0.f, 0.f, 0.f, coef[0], coef[1], coef[2]};
+  hipLaunchKernelGGL(k_g_plane_bar, DDH_G_GRID(P.N), pb2, P, S, pbar);
+  return hipGetLastError();
+}
+#undef DDH_G_GRID
+
 }  // namespace ddh

@@ -1098,4 +1098,210 @@ int ddh_fft2(int N, int count, const void* in, void* out, void* work, int invers
   return DDH_OK;
 }
 
+
+// ------------------------------------------------------- differentiation
+int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const float* phi0, const float* phi_true,
+                      int ckpt, float* d_phi0, ddh_grad_out* out, void* hip_stream) {
+  if (!p || !y || !phi0 || !phi_true || !d_phi0 || !out || K < 1 || ckpt < 1) return DDH_EINVAL;
+  int rc = validate(p);
+  if (rc != DDH_OK) return rc;
+  if (p->n_k != 1 || !(p->qg_p == 2.0f)) return DDH_EINVAL;
+  for (int k = 0; k < K; ++k)
+    if (!y[k]) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  DDH_CHECK(hipGetDevice(&dev));
+  float2* tw_all = nullptr;
+  rc = ensure_twiddles(dev, &tw_all);
+  if (rc != DDH_OK) return rc;
+  const int N = p->N;
+  const size_t px = (size_t)N * N;
+  const int nb = (int)((px + 255) / 256);
+  GradPrm P{};
+  P.N = N;
+  P.d2 = p->pupil_diameter * p->pupil_diameter;
+  P.lam = p->lambda;
+  P.alpha = p->alpha;
+  P.fl = p->r_floor;
+  P.s2 = p->sigma_w2;
+  P.inv_sp = (float)(1.0 / ((double)p->qg_sigma * (double)p->qg_sigma));
+  P.pmq = p->qg_p - p->qg_q;
+  P.lc = (float)(((double)p->qg_p - (double)p->qg_q) * std::log2(1.0 / ((double)p->qg_T * (double)p->qg_sigma)));
+  P.qop = p->qg_q / p->qg_p;
+  P.beta = p->beta_phi;
+  P.sig_r = p->qg_sigma;
+  // inverse of the pupil moment matrix (plane fit)
+  double minv[6];
+  {
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    const double c = 0.5 * (N - 1);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
+        if ((float)(di * di + dj * dj) > P.d2) continue;
+        const double a = i - c, b = j - c;
+        m[0] += 1, m[1] += a, m[2] += b, m[3] += a * a, m[4] += a * b, m[5] += b * b;
+      }
+    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
+    for (int q = 0; q < 6; ++q) minv[q] = det != 0.0 ? inv[q] : 0.0;
+  }
+  // ---- workspace: checkpoints, one segment of frame stashes, adjoint arrays
+  const int nseg = (K + ckpt - 1) / ckpt;
+  const int per_frame_f = 4 + 5 + 4;  // phip s kap tth | rs[0..4] | ps[1..4]
+  const int per_frame_c = 5;          // yh v b mu z
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_ck = take(2 * (size_t)nseg * px * 4);
+  const size_t o_st = take((size_t)ckpt * (per_frame_f * px * 4 + per_frame_c * px * 8));
+  const size_t o_work = take(px * 8);
+  const size_t o_r0 = take(px * 4);
+  const size_t o_bf = take(15 * px * 4);
+  const size_t o_bc = take(4 * px * 8);
+  const size_t o_part = take((size_t)nb * 3 * 8);
+  char* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, off);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(grad)");
+  std::vector<double> part(nb * 3);
+  auto sums = [&](double (&x)[3]) -> int {
+    DDH_CHECK(hipMemcpyAsync(part.data(), mem + o_part, sizeof(double) * nb * 3, hipMemcpyDeviceToHost, st));
+    DDH_CHECK(hipStreamSynchronize(st));
+    x[0] = x[1] = x[2] = 0.0;
+    for (int b = 0; b < nb; ++b)
+      for (int q = 0; q < 3; ++q) x[q] += part[b * 3 + q];
+    return DDH_OK;
+  };
+  double* dpart = (double*)(mem + o_part);
+  float* ck = (float*)(mem + o_ck);
+  auto ck_r = [&](int sgi) { return ck + (size_t)(2 * sgi) * px; };
+  auto ck_p = [&](int sgi) { return ck + (size_t)(2 * sgi + 1) * px; };
+  std::vector<GradFwd> slot(ckpt);
+  {
+    char* q = mem + o_st;
+    for (int t = 0; t < ckpt; ++t) {
+      GradFwd& a = slot[t];
+      float* fb = (float*)q;
+      a.phip = fb, a.s = fb + px, a.kap = fb + 2 * px, a.tth = fb + 3 * px;
+      for (int c = 0; c < 5; ++c) a.rs[c] = fb + (4 + c) * px;
+      a.ps[0] = nullptr;
+      for (int c = 1; c < 5; ++c) a.ps[c] = fb + (8 + c) * px;
+      float2* cb = (float2*)(q + per_frame_f * px * 4);
+      a.yh = cb, a.v = cb + px, a.b = cb + 2 * px, a.mu = cb + 3 * px, a.z = cb + 4 * px;
+      a.work = (float2*)(mem + o_work);
+      a.tw = tw_all + twiddle_offset(N);
+      a.prm = P;
+      q += per_frame_f * px * 4 + per_frame_c * px * 8;
+    }
+  }
+  float* rzero = (float*)(mem + o_r0);
+  GradBwd g{};
+  {
+    float* f = (float*)(mem + o_bf);
+    float** fp[15] = {&g.rbar, &g.pbar, &g.pb2, &g.em, &g.kbar, &g.tbar, &g.sbar, &g.Abar, &g.Bbar,
+                      &g.gs2, &g.gsr, &g.gbeta, nullptr, nullptr, nullptr};
+    for (int q = 0; q < 12; ++q) *fp[q] = f + q * px;
+    float2* c = (float2*)(mem + o_bc);
+    g.zbar = c, g.mubar = c + px, g.bbar = c + 2 * px, g.vbar = c + 3 * px;
+  }
+  auto fail = [&](int code) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    return code;
+  };
+  auto zero = [&](float* x, size_t n) { return launch_fill_zero(x, (long long)n, st); };
+  if (zero(rzero, px) != hipSuccess || zero((float*)(mem + o_bf), 15 * px) != hipSuccess)
+    return fail(DDH_EDEVICE);
+  // one frame forward into slot t from (r_in, phi_in)
+  auto frame = [&](int k, int t, const float* r_in, const float* phi_in) -> int {
+    GradFwd& a = slot[t];
+    a.y = static_cast<const float2*>(y[k]);
+    a.r_in = r_in;
+    a.phi_in = phi_in;
+    double x[3];
+    if (g_launch_ysum(a.y, N, dpart, st) != hipSuccess) return DDH_EDEVICE;
+    if (sums(x) != DDH_OK) return DDH_EDEVICE;
+    const double mr = x[0] / px, mi = x[1] / px;
+    const double m2 = x[2] - (double)px * (mr * mr + mi * mi);
+    if (!(m2 > 0.0) || !std::isfinite(m2)) return DDH_EDATA;
+    if (g_launch_psum(phi_in, N, P.d2, dpart, st) != hipSuccess) return DDH_EDEVICE;
+    if (sums(x) != DDH_OK) return DDH_EDEVICE;
+    a.scal = GradScal{(float)mr, (float)mi, (float)std::sqrt((double)px / m2),
+                      (float)(minv[0] * x[0] + minv[1] * x[1] + minv[2] * x[2]),
+                      (float)(minv[1] * x[0] + minv[3] * x[1] + minv[4] * x[2]),
+                      (float)(minv[2] * x[0] + minv[4] * x[1] + minv[5] * x[2])};
+    return g_launch_forward(a, st) == hipSuccess ? DDH_OK : DDH_EDEVICE;
+  };
+  // ---- forward with checkpoints
+  const float* r_cur = rzero;
+  const float* p_cur = phi0;
+  for (int k = 0; k < K; ++k) {
+    if (k % ckpt == 0) {
+      if (launch_copy(ck_r(k / ckpt), r_cur, (long long)px, st) != hipSuccess ||
+          launch_copy(ck_p(k / ckpt), p_cur, (long long)px, st) != hipSuccess)
+        return fail(DDH_EDEVICE);
+      r_cur = ck_r(k / ckpt);
+      p_cur = ck_p(k / ckpt);
+    }
+    const int t = k % ckpt;
+    rc = frame(k, t, r_cur, p_cur);
+    if (rc != DDH_OK) return fail(rc);
+    r_cur = slot[t].rs[4];
+    p_cur = slot[t].ps[4];
+  }
+  // ---- loss on the last phase
+  double x[3];
+  if (g_launch_dsum(p_cur, phi_true, N, P.d2, dpart, st) != hipSuccess || sums(x) != DDH_OK)
+    return fail(DDH_EDEVICE);
+  const double n = x[2], dmean = x[0] / n, var = x[1] / n - dmean * dmean;
+  const double L = std::sqrt(std::max(var, 0.0));
+  out->loss = L;
+  if (!(L > 0.0)) return fail(DDH_EDATA);
+  if (g_launch_loss_bar(p_cur, phi_true, slot[(K - 1) % ckpt], (float)dmean, (float)(1.0 / (n * L)), g.pbar, st) !=
+      hipSuccess)
+    return fail(DDH_EDEVICE);
+  // ---- backward, segment by segment (recomputing each segment's stashes)
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int k0 = sgi * ckpt, k1 = std::min(K, k0 + ckpt);
+    const float* rr = ck_r(sgi);
+    const float* pp = ck_p(sgi);
+    for (int k = k0; k < k1; ++k) {
+      rc = frame(k, k - k0, rr, pp);
+      if (rc != DDH_OK) return fail(rc);
+      rr = slot[k - k0].rs[4];
+      pp = slot[k - k0].ps[4];
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const GradFwd& a = slot[k - k0];
+      if (zero(g.kbar, px) != hipSuccess || zero(g.tbar, px) != hipSuccess || zero(g.sbar, px) != hipSuccess)
+        return fail(DDH_EDEVICE);
+      if (g_launch_backward(a, g, st) != hipSuccess) return fail(DDH_EDEVICE);
+      if (g_launch_psum(g.pb2, N, P.d2, dpart, st) != hipSuccess || sums(x) != DDH_OK) return fail(DDH_EDEVICE);
+      const float coef[3] = {(float)(minv[0] * x[0] + minv[1] * x[1] + minv[2] * x[2]),
+                             (float)(minv[1] * x[0] + minv[3] * x[1] + minv[4] * x[2]),
+                             (float)(minv[2] * x[0] + minv[4] * x[1] + minv[5] * x[2])};
+      if (g_launch_plane_bar(g.pb2, a, coef, g.pbar, st) != hipSuccess) return fail(DDH_EDEVICE);
+    }
+  }
+  // ---- outputs
+  if (launch_copy(d_phi0, g.pbar, (long long)px, st) != hipSuccess) return fail(DDH_EDEVICE);
+  const float big = 1e30f;
+  double gsum[3];
+  float* acc[3] = {g.gs2, g.gsr, g.gbeta};
+  for (int q = 0; q < 3; ++q) {
+    if (g_launch_psum(acc[q], N, big, dpart, st) != hipSuccess || sums(x) != DDH_OK) return fail(DDH_EDEVICE);
+    gsum[q] = x[0];
+  }
+  out->d_sigma_w = 2.0 * std::sqrt((double)p->sigma_w2) * gsum[0];
+  out->d_sigma_r = gsum[1];
+  out->d_beta = gsum[2];
+  return fail(DDH_OK);
+}
+
 }  // extern "C"

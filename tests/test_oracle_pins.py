@@ -537,3 +537,33 @@ def test_true_phase_is_a_fixed_point_of_noise_free_phase_step():
     z_off = ddh.F(ddh.e_step(np.full((N, N), 1e12), ddh.back_project(yhat, phi_off, a), 1e-9)[0])
     theta = np.angle(yhat * np.conj(z_off))
     np.testing.assert_allclose(np.angle(np.exp(1j * (theta[m] - phi_off[m]))), 0.0, atol=1e-9)
+
+
+def test_reference_gradient_against_central_differences():
+    """FP64 autograd of the unrolled frames against central differences of the
+    NumPy oracle's loss (the forwards agree exactly first)."""
+    from oracle import grad as G
+    N, K = 16, 3
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=3, stream_id=0))
+    a = ddh.aperture(N)
+    frames = [st.frame(n) for n in range(K)]
+    ptrue = st.phase(K - 1)
+    prm = ddh.Params(sigma_w2=st.sigma_w2)
+    sw, sr, bt = float(np.sqrt(st.sigma_w2)), 0.2, 0.5
+    rng = np.random.default_rng(0)
+    phi0 = ddh.remove_tiptilt(0.3 * rng.standard_normal((N, N)), a)
+    L, g0, gsw, gsr, gbt = G.reference_gradient(phi0, sw, sr, bt, frames, ptrue, a, prm)
+    assert abs(L - G.oracle_loss(phi0, sw, sr, bt, frames, ptrue, a, prm)) <= 1e-12 * L
+    args = [sw, sr, bt]
+    for idx, g, h in ((0, gsw, 1e-6), (1, gsr, 1e-3), (1, gsr, 1e-5), (2, gbt, 1e-3), (2, gbt, 1e-5)):
+        up, dn = list(args), list(args)
+        up[idx] += h
+        dn[idx] -= h
+        fd = (G.oracle_loss(phi0, *up, frames, ptrue, a, prm) - G.oracle_loss(phi0, *dn, frames, ptrue, a, prm)) / (2 * h)
+        assert abs(fd - g) <= 2e-3 * abs(g), (idx, h, fd, g)
+    d = ddh.remove_tiptilt(rng.standard_normal((N, N)), a)
+    d /= np.sqrt(np.mean(d[a > 0] ** 2))
+    h = 1e-6
+    fd = (G.oracle_loss(phi0 + h * d, sw, sr, bt, frames, ptrue, a, prm)
+          - G.oracle_loss(phi0 - h * d, sw, sr, bt, frames, ptrue, a, prm)) / (2 * h)
+    assert abs(fd - np.sum(g0 * d)) <= 2e-3 * abs(fd)
