@@ -59,6 +59,9 @@ def parse():
     p.add_argument("--quality", action="store_true", help="instead: Strehl over the frames for N_k in {1,2,4,8} "
                    "(10 seeds) and over an alpha/lambda grid")
     p.add_argument("--quality-frames", type=int, default=150)
+    p.add_argument("--grad", action="store_true", help="instead: gradient of 8 unrolled frames for 16 streams at "
+                   "N=256 (hand-written adjoint, checkpoints every 2 frames)")
+    p.add_argument("--grad-rounds", type=int, default=5)
     return p.parse_args()
 
 
@@ -292,6 +295,76 @@ def quality_main(args, pre):
     print(json.dumps(out), flush=True)
 
 
+def grad_main(args):
+    """Differentiation workload: 16 streams at N=256, each with the gradient
+    of K=8 unrolled DDH frames (from r = 0 and a perturbed phase) with respect
+    to phi0, sigma_w, sigma_r and beta_phi, checkpoints every 2 frames.  The
+    frames and phases are resident on the device; one step is the 16
+    gradients in one batched call (ddh_unrolled_grad_batch), also timed as 16
+    single-stream calls.  The FP64 autograd reference (the oracle) is timed on
+    one stream."""
+    import torch
+    import paper_2305_03284_amd as D
+    import ddh_synth as synth
+    N, K, S, ckpt = 256, 8, 16, 2
+    v = synth.DEFAULT_PARAMS
+    cases = []
+    for sid in range(S):
+        st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=3, stream_id=sid))
+        rng = np.random.default_rng(sid)
+        phi0 = st.phase(0) + 0.3 * rng.standard_normal((N, N))
+        cases.append((st, [st.frame(n) for n in range(K)], phi0, st.phase(K - 1)))
+    dev = []
+    for st, frames, phi0, ptrue in cases:
+        prm = D.make_params(N, pupil_diameter=float(N), lam=v["lam"], alpha=v["alpha"], n_k=1,
+                            sigma_w2=st.sigma_w2, qg_q=v["qg_q"], qg_T=v["qg_T"], qg_sigma=v["qg_sigma"],
+                            beta_phi=v["beta_phi"], r_floor=v["r_floor"])
+        dev.append((prm, [torch.from_numpy(f).cuda() for f in frames],
+                    torch.from_numpy(phi0.astype(np.float32)).cuda(), torch.from_numpy(ptrue.astype(np.float32)).cuda()))
+
+    cols = list(zip(*dev))
+
+    def batched():
+        return D.unrolled_grad_batch(list(cols[0]), list(cols[1]), list(cols[2]), list(cols[3]), ckpt)
+
+    def one_at_a_time():
+        return [D.unrolled_grad(prm, ys, p0, pt, ckpt) for prm, ys, p0, pt in dev]
+
+    def timed(fn, rounds):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / rounds, res
+
+    dt, res = timed(batched, args.grad_rounds)
+    dt1, _ = timed(one_at_a_time, max(1, args.grad_rounds // 2))
+    out = {"metric": "unrolled-frame gradients/s", "value": S * K / dt, "unit": "frames/s", "n_gpus": 1,
+           "steps": args.grad_rounds, "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{S} streams x N={N}, gradient of K={K} unrolled DDH frames (N_k=1) w.r.t. "
+                                  f"phi0, sigma_w, sigma_r, beta_phi, checkpoints every {ckpt}",
+                      "streams": S, "N": N, "K": K, "ckpt": ckpt},
+           "one_stream_at_a_time": {"frames_per_s": S * K / dt1, "ms_per_step": dt1 * 1e3},
+           "mean_loss": float(np.mean([r[0] for r in res]))}
+    if not args.no_cpu_baseline:
+        from oracle import grad as G
+        from oracle import ddh as O
+        st, frames, phi0, ptrue = cases[0]
+        a = O.aperture(N)
+        prm0 = O.Params(sigma_w2=st.sigma_w2)
+        t0 = time.perf_counter()
+        G.reference_gradient(phi0, float(np.sqrt(st.sigma_w2)), prm0.qg_sigma, prm0.beta_phi, frames, ptrue, a, prm0)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": K / t_cpu, "unit": "frames/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle",
+                               "sample": f"one stream's gradient of {K} frames at N={N}, FP64 torch autograd on the "
+                                         f"host, {t_cpu:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -312,6 +385,9 @@ def main():
         return
     if args.quality:
         quality_main(args, pre)
+        return
+    if args.grad:
+        grad_main(args)
         return
     import paper_2305_03284_amd as D
     import ddh_synth as synth

@@ -231,6 +231,22 @@ typedef struct {
 int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const float* phi0, const float* phi_true,
                       int ckpt, float* d_phi0, ddh_grad_out* out, void* hip_stream);
 
+/* The same for `count` independent streams of one N in one pass: each kernel
+ * covers every stream (the stream is the grid's second dimension), and the
+ * FP64 reductions are combined on the device, so the call synchronises
+ * hip_stream once.  p: host array of count parameter sets (same N; n_k = 1,
+ * qg_p = 2); y: host array of count*K device frame pointers, stream-major
+ * (y[b*K + k] is frame k of stream b); phi0, phi_true, d_phi0: host arrays of
+ * count device pointers (N*N floats each); out: host array of count results.
+ * Each stream's results are bit-identical to ddh_unrolled_grad on that stream
+ * alone.  Workspace about (8 ceil(K/ckpt) + 92 ckpt + 100) bytes per pixel per
+ * stream.  DDH_EINVAL for mixed N or a null pointer; DDH_EDATA if a frame of
+ * any stream cannot be normalised or a loss is zero (the other streams'
+ * results are still written); DDH_EINVAL also if count*N*N exceeds 2^31 - 1. */
+int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* const* y, const float* const* phi0,
+                            const float* const* phi_true, int ckpt, float* const* d_phi0, ddh_grad_out* out,
+                            void* hip_stream);
+
 /* ---------------------------------------------------------- FFT (a3, a6) */
 
 /* Batched unitary 2D DFT of `count` N x N complex64 images (device pointers,

@@ -172,7 +172,7 @@ def reference_gradient(phi0: np.ndarray, sigma_w: float, sigma_r: float, beta: f
     bt = torch.tensor(float(beta), dtype=_T, requires_grad=True)
     L = unrolled_loss(p0, sw, sr, bt, frames, phi_true, a, prm)
     L.backward()
-    return float(L), p0.grad.numpy().copy(), float(sw.grad), float(sr.grad), float(bt.grad)
+    return float(L.detach()), p0.grad.numpy().copy(), float(sw.grad), float(sr.grad), float(bt.grad)
 
 
 def oracle_loss(phi0: np.ndarray, sigma_w: float, sigma_r: float, beta: float, frames, phi_true, a,

@@ -67,6 +67,9 @@ SIGNATURES = {
                                  _c_void_p]),
     "ddh_unrolled_grad": (_c_int, [ctypes.POINTER(Params), _c_int, ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p,
                                    _c_int, _c_void_p, ctypes.POINTER(GradOut), _c_void_p]),
+    "ddh_unrolled_grad_batch": (_c_int, [ctypes.POINTER(Params), _c_int, _c_int, ctypes.POINTER(_c_void_p),
+                                         ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int,
+                                         ctypes.POINTER(_c_void_p), ctypes.POINTER(GradOut), _c_void_p]),
     "ddh_fft2": (_c_int, [_c_int, _c_int, _c_void_p, _c_void_p, _c_void_p, _c_int, _c_void_p]),
     "ddh_set_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
     "ddh_get_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
@@ -349,6 +352,37 @@ def unrolled_grad(params: Params, frames, phi0, phi_true, ckpt: int = 2):
     return out.loss, g, out.d_sigma_w, out.d_sigma_r, out.d_beta
 
 
+def unrolled_grad_batch(params, frames, phi0, phi_true, ckpt: int = 2):
+    """unrolled_grad for several streams of one N in one pass
+    (ddh_unrolled_grad_batch).  params, frames (a list of K frames per
+    stream), phi0, phi_true: one entry per stream.  Returns a list of
+    (loss, d/dphi0, d/dsigma_w, d/dqg_sigma, d/dbeta_phi) per stream."""
+    torch = _torch()
+    B = len(params)
+    if not (B >= 1 and len(frames) == B and len(phi0) == B and len(phi_true) == B):
+        raise ValueError("params, frames, phi0 and phi_true need one entry per stream")
+    K = len(frames[0])
+    N = params[0].N
+    for b in range(B):
+        if params[b].N != N or len(frames[b]) != K:
+            raise ValueError("all streams need the same N and the same number of frames")
+        for y in frames[b]:
+            _check_frame(y, N)
+        for x in (phi0[b], phi_true[b]):
+            if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and tuple(x.shape) == (N, N)):
+                raise ValueError("phi0 and phi_true must be contiguous float32 CUDA tensors of shape (N, N)")
+    prm = (Params * B)(*params)
+    ys = (ctypes.c_void_p * (B * K))(*[y.data_ptr() for fr in frames for y in fr])
+    grads = [torch.empty((N, N), dtype=torch.float32, device=phi0[0].device) for _ in range(B)]
+    p0 = (ctypes.c_void_p * B)(*[x.data_ptr() for x in phi0])
+    pt = (ctypes.c_void_p * B)(*[x.data_ptr() for x in phi_true])
+    gp = (ctypes.c_void_p * B)(*[x.data_ptr() for x in grads])
+    outs = (GradOut * B)()
+    _check(lib().ddh_unrolled_grad_batch(prm, B, K, ys, p0, pt, int(ckpt), gp, outs, _stream_ptr()),
+           "ddh_unrolled_grad_batch")
+    return [(o.loss, g, o.d_sigma_w, o.d_sigma_r, o.d_beta) for o, g in zip(outs, grads)]
+
+
 def unrolled_loss_fn():
     """torch.autograd.Function over unrolled_grad: forward(phi0, sigma_w,
     sigma_r, beta, frames, phi_true, base_params, ckpt) -> loss; backward
@@ -414,5 +448,5 @@ def autotune(N: int, count: int):
     return tuple(cfg), tuple(us)
 
 
-__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_grad_batch", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

@@ -113,41 +113,52 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st
 hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st);
 
 // --- unrolled frames with a hand-written adjoint (ddh_kernels.hip) ---------
-// frame scalars: normalisation and the tip/tilt plane (host-combined FP64 sums)
+// frame scalars: normalisation and the tip/tilt plane (FP64 sums combined on the device)
 struct GradScal {
   float mu_re, mu_im, scale, c0, c1, c2;
 };
-// constants of the differentiated stream (sig_r: QGGMRF scale, for its gradient)
+// one stream's constants (a device array of these, one per stream of a batch)
 struct GradPrm {
   int N;
   float d2, lam, alpha, fl, s2, inv_sp, lc, pmq, qop, beta, sig_r;
 };
-// one frame's inputs, intermediates and outputs (device arrays of N*N)
+struct GradLoss {
+  float dmean, inv_nL;
+  double loss;
+};
+// device scalars of a batch of B streams of one N
+struct GradDev {
+  const GradPrm* prm;  // [B]
+  const double* minv;  // [B][6] inverse pupil moment matrix (symmetric, upper triangle)
+  GradScal* scal;      // [B] Normalize and plane of the frame being run
+  GradScal* bscal;     // [B] plane of the phase adjoint
+  GradLoss* loss;      // [B]
+  double* tot;         // [B][3] sums of gs2, gsr, gbeta
+  int* flag;           // [B] bit 1: a frame could not be normalised; bit 2: zero loss
+  double* part;        // [B][nb][3] FP64 block partials
+};
+// one frame's inputs, intermediates and outputs; arrays are B images of N*N
+// back to back
 struct GradFwd {
-  const float2* y;
+  const float2* const* y;  // device table of the B streams' frames
   const float* phi_in;
   const float* r_in;
-  GradPrm prm;
-  GradScal scal;
   float2 *yh, *v, *b, *mu, *z, *work;
   float *phip, *s, *kap, *tth;
   float* rs[5];  // r before colour pass c (rs[0] = Eq. (3) value), rs[4] = output
   float* ps[5];  // phi after colour pass c-1 (ps[4] = output); pass 0 reads phip
   const float2* tw;
 };
-// adjoint work arrays (device, N*N); gs2, gsr, gbeta accumulate per pixel
+// adjoint work arrays (B images of N*N); gs2, gsr, gbeta accumulate per pixel
 struct GradBwd {
   float *rbar, *pbar, *pb2, *em, *kbar, *tbar, *sbar, *Abar, *Bbar;
   float2 *zbar, *mubar, *bbar, *vbar;
   float *gs2, *gsr, *gbeta;
 };
-hipError_t g_launch_ysum(const float2* y, int N, double* part, hipStream_t st);
-hipError_t g_launch_psum(const float* f, int N, float d2, double* part, hipStream_t st);
-hipError_t g_launch_dsum(const float* phi, const float* ptrue, int N, float d2, double* part, hipStream_t st);
-hipError_t g_launch_forward(const GradFwd& a, hipStream_t st);
-hipError_t g_launch_loss_bar(const float* phi, const float* ptrue, const GradFwd& a, float dmean, float inv_nL,
-                             float* pbar, hipStream_t st);
-hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, hipStream_t st);
-hipError_t g_launch_plane_bar(const float* pb2, const GradFwd& a, const float* coef, float* pbar, hipStream_t st);
+hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st);
+hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d, int N, int B, float* pbar,
+                         hipStream_t st);
+hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st);
+hipError_t g_launch_totals(const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st);
 
 }  // namespace ddh

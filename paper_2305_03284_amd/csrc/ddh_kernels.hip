@@ -1660,7 +1660,11 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st
 // sigma_r and the phase-prior weight beta).  Plain whole-image kernels, one
 // thread per pixel, no fusion: they keep every intermediate the adjoint needs.
 // The forward uses the same per-pixel helpers as the fast path (the colour
-// passes are those of k_mpass).  Arrays are N x N, row-major.
+// passes are those of k_mpass).  One launch covers a batch of streams of one
+// N: blockIdx.y is the stream, every array is the streams' N x N row-major
+// images back to back, and each stream's constants and per-frame scalars sit
+// in device arrays indexed by the stream.  The scalar reductions (Normalize,
+// the tip/tilt plane, the loss) are FP64 block partials combined on the device.
 // ===========================================================================
 
 
@@ -1670,6 +1674,8 @@ __device__ __forceinline__ bool g_pix(int& i, int& j, int N) {
   j = p - i * N;
   return p < N * N;
 }
+// index of pixel (i, j) of this block's stream in a batched array
+__device__ __forceinline__ int g_at(int i, int j, int N) { return ((int)blockIdx.y * N + i) * N + j; }
 __device__ __forceinline__ void g_block_sums(double (&x)[3], double* part) {
   __shared__ double red[3][4];
 #pragma unroll
@@ -1681,15 +1687,16 @@ __device__ __forceinline__ void g_block_sums(double (&x)[3], double* part) {
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) part[blockIdx.x * 3 + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+    for (int k = 0; k < 3; ++k)
+      part[(blockIdx.y * gridDim.x + blockIdx.x) * 3 + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
 }
 
 // sums of Re y, Im y, |y|^2 (FP64 block partials)
-__global__ __launch_bounds__(256) void k_g_ysum(const float2* y, int N, double* part) {
+__global__ __launch_bounds__(256) void k_g_ysum(const float2* const* ys, int N, double* part) {
   int i, j;
   double x[3] = {0, 0, 0};
   if (g_pix(i, j, N)) {
-    const float2 v = y[i * N + j];
+    const float2 v = ys[blockIdx.y][i * N + j];
     x[0] = v.x;
     x[1] = v.y;
     x[2] = (double)v.x * v.x + (double)v.y * v.y;
@@ -1697,11 +1704,13 @@ __global__ __launch_bounds__(256) void k_g_ysum(const float2* y, int N, double* 
   g_block_sums(x, part);
 }
 // plane-fit sums over the pupil of f: sum f, sum (i-c) f, sum (j-c) f
-__global__ __launch_bounds__(256) void k_g_psum(const float* f, int N, float d2, double* part) {
+__global__ __launch_bounds__(256) void k_g_psum(const float* f, const GradPrm* Pd, double* part) {
+  const int N = Pd[blockIdx.y].N;
+  const float d2 = Pd[blockIdx.y].d2;
   int i, j;
   double x[3] = {0, 0, 0};
   if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
-    const double c = 0.5 * (N - 1), v = f[i * N + j];
+    const double c = 0.5 * (N - 1), v = f[g_at(i, j, N)];
     x[0] = v;
     x[1] = (i - c) * v;
     x[2] = (j - c) * v;
@@ -1709,11 +1718,15 @@ __global__ __launch_bounds__(256) void k_g_psum(const float* f, int N, float d2,
   g_block_sums(x, part);
 }
 // piston-removed phase error sums over the pupil: sum d, sum d^2, d = phi - phi_true
-__global__ __launch_bounds__(256) void k_g_dsum(const float* phi, const float* ptrue, int N, float d2, double* part) {
+__global__ __launch_bounds__(256) void k_g_dsum(const float* phi, const float* ptrue, const GradPrm* Pd,
+                                                double* part) {
+  const int N = Pd[blockIdx.y].N;
+  const float d2 = Pd[blockIdx.y].d2;
   int i, j;
   double x[3] = {0, 0, 0};
   if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
-    const double d = (double)phi[i * N + j] - ptrue[i * N + j];
+    const int p = g_at(i, j, N);
+    const double d = (double)phi[p] - ptrue[p];
     x[0] = d;
     x[1] = d * d;
     x[2] = 1.0;
@@ -1721,13 +1734,81 @@ __global__ __launch_bounds__(256) void k_g_dsum(const float* phi, const float* p
   g_block_sums(x, part);
 }
 
+// sums over the whole image of the three per-pixel gradient accumulators
+__global__ __launch_bounds__(256) void k_g_tsum(const float* a0, const float* a1, const float* a2, int N,
+                                                double* part) {
+  int i, j;
+  double x[3] = {0, 0, 0};
+  if (g_pix(i, j, N)) {
+    const int p = g_at(i, j, N);
+    x[0] = a0[p];
+    x[1] = a1[p];
+    x[2] = a2[p];
+  }
+  g_block_sums(x, part);
+}
+// One block per stream: the stream's nb block partials, summed in FP64, turned
+// into the scalars the next kernels read.
+//   G_NORM : Normalize (Eq. 4): mean and 1/std of y -> S (flag bit 1 if y is constant)
+//   G_PLANE: least-squares plane c = M^{-1} (sum f, sum (i-c) f, sum (j-c) f) -> S
+//   G_LOSS : piston-removed RMS phase error -> Lo (flag bit 2 if it is zero)
+//   G_TOTAL: the three sums -> tot
+enum { G_NORM = 0, G_PLANE = 1, G_LOSS = 2, G_TOTAL = 3 };
+template <int MODE>
+__global__ __launch_bounds__(256) void k_g_combine(const double* part, int nb, int N, const double* minv,
+                                                   GradScal* S, GradLoss* Lo, double* tot, int* flag) {
+  const int b = blockIdx.x;
+  double x[3] = {0, 0, 0};
+  for (int q = threadIdx.x; q < nb; q += 256)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[k] += part[((size_t)b * nb + q) * 3 + k];
+  __shared__ double red[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = wave_sum_d(x[k]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k][wv] = x[k];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+  if constexpr (MODE == G_NORM) {
+    const double px = (double)N * N, mr = t[0] / px, mi = t[1] / px;
+    const double m2 = t[2] - px * (mr * mr + mi * mi);
+    const bool ok = m2 > 0.0 && m2 < HUGE_VAL;
+    S[b].mu_re = (float)mr;
+    S[b].mu_im = (float)mi;
+    S[b].scale = ok ? (float)sqrt(px / m2) : 0.0f;
+    if (!ok) flag[b] = flag[b] | 1;
+  } else if constexpr (MODE == G_PLANE) {
+    const double* M = minv + 6 * b;
+    S[b].c0 = (float)(M[0] * t[0] + M[1] * t[1] + M[2] * t[2]);
+    S[b].c1 = (float)(M[1] * t[0] + M[3] * t[1] + M[4] * t[2]);
+    S[b].c2 = (float)(M[2] * t[0] + M[4] * t[1] + M[5] * t[2]);
+  } else if constexpr (MODE == G_LOSS) {
+    const double n = t[2], dmean = t[0] / n, var = t[1] / n - dmean * dmean;
+    const double L = sqrt(var > 0.0 ? var : 0.0);
+    Lo[b].dmean = (float)dmean;
+    Lo[b].inv_nL = L > 0.0 ? (float)(1.0 / (n * L)) : 0.0f;
+    Lo[b].loss = L;
+    if (!(L > 0.0)) flag[b] = flag[b] | 2;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tot[3 * b + k] = t[k];
+  }
+}
+
 // frame prologue: yhat, phi' (plane removed, zero off the pupil), v = a exp(-j phi') yhat
-__global__ __launch_bounds__(256) void k_g_prologue(const float2* y, const float* phi, GradPrm P, GradScal S,
-                                                    float2* yh, float* phip, float2* v) {
+__global__ __launch_bounds__(256) void k_g_prologue(const float2* const* ys, const float* phi, const GradPrm* Pd,
+                                                    const GradScal* Sd, float2* yh, float* phip, float2* v) {
+  const GradPrm P = Pd[blockIdx.y];
+  const GradScal S = Sd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
-  const float2 yy = y[p];
+  const int p = g_at(i, j, P.N);
+  const float2 yy = ys[blockIdx.y][i * P.N + j];
   const float2 h = make_float2((yy.x - S.mu_re) * S.scale, (yy.y - S.mu_im) * S.scale);
   yh[p] = h;
   float ph = 0.f;
@@ -1742,11 +1823,12 @@ __global__ __launch_bounds__(256) void k_g_prologue(const float2* y, const float
   v[p] = vv;
 }
 // Eq. (3) and the E-step: r0, mu (into mu), s
-__global__ __launch_bounds__(256) void k_g_estep(const float* rprev, const float2* b, GradPrm P, float* r0, float2* mu,
-                                                 float* s) {
+__global__ __launch_bounds__(256) void k_g_estep(const float* rprev, const float2* b, const GradPrm* Pd, float* r0,
+                                                 float2* mu, float* s) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   const float2 bv = b[p];
   const float bb = bv.x * bv.x + bv.y * bv.y;
   const float r = rinit_of(rprev[p], bb, P.lam, P.alpha, P.fl);
@@ -1763,11 +1845,12 @@ __device__ __forceinline__ void g_data_u(float2 h, float ph, float2 z, float& ur
   ur = cs * qr - sn * qi;
   ui = sn * qr + cs * qi;
 }
-__global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* phip, const float2* z, GradPrm P,
+__global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* phip, const float2* z, const GradPrm* Pd,
                                                 float* kap, float* tth) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   float ka = 0.f, tt = 0.f;
   if (in_pupil(i, j, P.N, P.d2)) {
     float ur, ui;
@@ -1782,10 +1865,11 @@ __global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* p
 }
 // colour pass C of the r M-step, out of place (rin -> rout)
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* s, GradPrm P, float* rout) {
+__global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* s, const GradPrm* Pd, float* rout) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   if ((i & 1) + 2 * (j & 1) != C) {
     rout[p] = rin[p];
     return;
@@ -1804,11 +1888,12 @@ __global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* 
 }
 // colour pass C of the phi M-step, out of place
 template <int C>
-__global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* kap, const float* tth, GradPrm P,
-                                                 float* pout) {
+__global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* kap, const float* tth,
+                                                 const GradPrm* Pd, float* pout) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) {
     pout[p] = pin[p];
     return;
@@ -1828,22 +1913,25 @@ __global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* 
 
 // ---------------------------------------------------------------- adjoint
 // loss: L = sqrt(mean(d - mean d)^2) over the pupil; dL/dphi = (d - mean d)/(n L)
-__global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const float* ptrue, GradPrm P, float dmean,
-                                                    float inv_nL, float* pbar) {
+__global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const float* ptrue, const GradPrm* Pd,
+                                                    const GradLoss* Lo, float* pbar) {
+  const GradPrm P = Pd[blockIdx.y];
+  const float dmean = Lo[blockIdx.y].dmean, inv_nL = Lo[blockIdx.y].inv_nL;
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   pbar[p] = in_pupil(i, j, P.N, P.d2) ? (phi[p] - ptrue[p] - dmean) * inv_nL : 0.f;
 }
 // phi pass C reversed, part a: the colour-C pupil pixels hand their adjoint to
 // kappa, theta~, beta and (as em = pbar 2 beta / den) to their neighbours
 template <int C>
 __global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float* pout, const float* kap,
-                                                   const float* tth, GradPrm P, float* pbar, float* em, float* kbar,
-                                                   float* tbar, float* gbeta) {
+                                                   const float* tth, const GradPrm* Pd, float* pbar, float* em,
+                                                   float* kbar, float* tbar, float* gbeta) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   em[p] = 0.f;
   if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) return;
   const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
@@ -1851,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ii = i + nb[e][0], jj = j + nb[e][1];
-    if (ii >= 0 && ii < N && jj >= 0 && jj < N) Ph += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * pin[ii * N + jj];
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N) Ph += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * pin[g_at(ii, jj, N)];
   }
   const float Pw = pupil_weight_of(pupil_nbr_12(i, j, N, P.d2));
   const float ka = kap[p], beta2 = 2.0f * P.beta;
@@ -1865,27 +1953,29 @@ __global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float
   pbar[p] = 0.f;
 }
 // part b: pupil pixels gather em of their colour-C pupil neighbours
-__global__ __launch_bounds__(256) void k_g_pback_b(const float* em, GradPrm P, float* pbar) {
+__global__ __launch_bounds__(256) void k_g_pback_b(const float* em, const GradPrm* Pd, float* pbar) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   if (!in_pupil(i, j, N, P.d2)) return;
   const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
   float acc = 0.f;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ii = i + nb[e][0], jj = j + nb[e][1];
-    if (ii >= 0 && ii < N && jj >= 0 && jj < N) acc += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * em[ii * N + jj];
+    if (ii >= 0 && ii < N && jj >= 0 && jj < N) acc += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * em[g_at(ii, jj, N)];
   }
   pbar[p] += acc;
 }
 // data term reversed: (kbar, tbar) -> phi' (pb2 += ...), z (zbar), s2
 __global__ __launch_bounds__(256) void k_g_data_bar(const float2* yh, const float* phip, const float2* z,
-                                                    const float* kap, const float* kbar, const float* tbar, GradPrm P,
-                                                    float* pb2, float2* zbar, float* gs2) {
+                                                    const float* kap, const float* kbar, const float* tbar,
+                                                    const GradPrm* Pd, float* pb2, float2* zbar, float* gs2) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   zbar[p] = make_float2(0.f, 0.f);
   if (!in_pupil(i, j, P.N, P.d2)) return;
   float ur, ui;
@@ -1933,11 +2023,13 @@ __device__ __forceinline__ void g_shape(float d, const GradPrm& P, float& sh, fl
 // r pass C reversed, part a: colour-C pixels turn their adjoint into (Abar,
 // Bbar, sbar), their own old value's adjoint and the sigma_r gradient
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float* rout, const float* s, GradPrm P,
-                                                   float* rbar, float* sbar, float* Abar, float* Bbar, float* gsr) {
+__global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float* rout, const float* s,
+                                                   const GradPrm* Pd, float* rbar, float* sbar, float* Abar,
+                                                   float* Bbar, float* gsr) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   Abar[p] = 0.f;
   Bbar[p] = 0.f;
   if ((i & 1) + 2 * (j & 1) != C) return;
@@ -1950,7 +2042,7 @@ __global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float
   for (int e = 0; e < 8; ++e) {
     const int ii = i + nb[e][0], jj = j + nb[e][1];
     ok[e] = ii >= 0 && ii < N && jj >= 0 && jj < N;
-    rq[e] = ok[e] ? rin[ii * N + jj] : 0.f;
+    rq[e] = ok[e] ? rin[g_at(ii, jj, N)] : 0.f;
     W[e] = ok[e] ? P.inv_sp * (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) : 0.f;
     g_shape(ri - rq[e], P, sh[e], dsh[e], dss[e]);
     A += W[e] * sh[e];
@@ -1985,11 +2077,12 @@ __global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float
 }
 // part b: every pixel not of colour C gathers from its colour-C neighbours
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float* Abar, const float* Bbar, GradPrm P,
-                                                   float* rbar) {
+__global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float* Abar, const float* Bbar,
+                                                   const GradPrm* Pd, float* rbar) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = i * N + j;
+  const int N = P.N, p = g_at(i, j, N);
   if ((i & 1) + 2 * (j & 1) == C) return;
   const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
   const float rj = rin[p];
@@ -1998,7 +2091,7 @@ __global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float
   for (int e = 0; e < 8; ++e) {
     const int ii = i + nb[e][0], jj = j + nb[e][1];
     if (!(ii >= 0 && ii < N && jj >= 0 && jj < N)) continue;
-    const int q = ii * N + jj;
+    const int q = g_at(ii, jj, N);
     if ((ii & 1) + 2 * (jj & 1) != C) continue;
     const float ab = Abar[q], bb = Bbar[q];
     if (ab == 0.0f && bb == 0.0f) continue;
@@ -2011,11 +2104,12 @@ __global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float
 }
 // E-step and Eq. (3) reversed: (mubar, sbar, r0bar) -> bbar, rbar of the previous state, s2
 __global__ __launch_bounds__(256) void k_g_estep_bar(const float* rprev, const float2* b, const float* r0,
-                                                     const float2* mubar, const float* sbar, GradPrm P, float* rbar,
-                                                     float2* bbar, float* gs2) {
+                                                     const float2* mubar, const float* sbar, const GradPrm* Pd,
+                                                     float* rbar, float2* bbar, float* gs2) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   const float2 bv = b[p], mb = mubar[p];
   const float bb = bv.x * bv.x + bv.y * bv.y;
   const float r = r0[p], den = r + P.s2, w = r / den;
@@ -2036,11 +2130,12 @@ __global__ __launch_bounds__(256) void k_g_estep_bar(const float* rprev, const f
   gs2[p] += g2;
 }
 // back-projection reversed: phi' adjoint += Im(conj(vbar) v), v = a exp(-j phi') yhat
-__global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const float2* yh, const float* phip, GradPrm P,
-                                                  float* pb2) {
+__global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const float2* yh, const float* phip,
+                                                  const GradPrm* Pd, float* pb2) {
+  const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   if (!in_pupil(i, j, P.N, P.d2)) return;
   float sn, cs;
   fsincos(phip[p], &sn, &cs);
@@ -2048,90 +2143,100 @@ __global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const floa
   pb2[p] += vb.x * v.y - vb.y * v.x;
 }
 // tip/tilt removal reversed: pbar = pupil ? pb2 - plane(pb2) : 0
-__global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, GradPrm P, GradScal S, float* pbar) {
+__global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, const GradPrm* Pd, const GradScal* Sd,
+                                                     float* pbar) {
+  const GradPrm P = Pd[blockIdx.y];
+  const GradScal S = Sd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
-  const int p = i * P.N + j;
+  const int p = g_at(i, j, P.N);
   pbar[p] = in_pupil(i, j, P.N, P.d2) ? pb2[p] - plane_val(S.c0, S.c1, S.c2, i, j, P.N) : 0.f;
 }
 
-#define DDH_G_GRID(N) dim3(((N) * (N) + 255) / 256), dim3(256), 0, st
-hipError_t g_launch_ysum(const float2* y, int N, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_g_ysum, DDH_G_GRID(N), y, N, part);
-  return hipGetLastError();
-}
-hipError_t g_launch_psum(const float* f, int N, float d2, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N), f, N, d2, part);
-  return hipGetLastError();
-}
-hipError_t g_launch_dsum(const float* phi, const float* ptrue, int N, float d2, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_g_dsum, DDH_G_GRID(N), phi, ptrue, N, d2, part);
-  return hipGetLastError();
-}
-hipError_t g_launch_forward(const GradFwd& a, hipStream_t st) {
-  const GradPrm P = a.prm;
-  const GradScal S = a.scal;
-  const int N = P.N;
-  hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N), a.y, a.phi_in, P, S, a.yh, a.phip, a.v);
-  hipError_t e = launch_fft2(N, 1, a.v, a.b, a.work, a.tw, 1, st);
+#define DDH_G_GRID(N, B) dim3(((N) * (N) + 255) / 256, (B)), dim3(256), 0, st
+static int g_nb(int N) { return (N * N + 255) / 256; }
+
+hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st) {
+  const int nb = g_nb(N);
+  // Normalize and the tip/tilt plane of the incoming phase
+  hipLaunchKernelGGL(k_g_ysum, DDH_G_GRID(N, B), a.y, N, d.part);
+  hipLaunchKernelGGL(k_g_combine<G_NORM>, dim3(B), dim3(256), 0, st, d.part, nb, N, d.minv, d.scal, d.loss, d.tot,
+                     d.flag);
+  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N, B), a.phi_in, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_combine<G_PLANE>, dim3(B), dim3(256), 0, st, d.part, nb, N, d.minv, d.scal, d.loss, d.tot,
+                     d.flag);
+  hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N, B), a.y, a.phi_in, d.prm, d.scal, a.yh, a.phip, a.v);
+  hipError_t e = launch_fft2(N, B, a.v, a.b, a.work, a.tw, 1, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_estep, DDH_G_GRID(N), a.r_in, a.b, P, a.rs[0], a.mu, a.s);
-  e = launch_fft2(N, 1, a.mu, a.z, a.work, a.tw, 0, st);
+  hipLaunchKernelGGL(k_g_estep, DDH_G_GRID(N, B), a.r_in, a.b, d.prm, a.rs[0], a.mu, a.s);
+  e = launch_fft2(N, B, a.mu, a.z, a.work, a.tw, 0, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N), a.yh, a.phip, a.z, P, a.kap, a.tth);
-  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_GRID(N), a.rs[0], a.s, P, a.rs[1]);
-  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_GRID(N), a.rs[1], a.s, P, a.rs[2]);
-  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_GRID(N), a.rs[2], a.s, P, a.rs[3]);
-  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_GRID(N), a.rs[3], a.s, P, a.rs[4]);
-  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_GRID(N), a.phip, a.kap, a.tth, P, a.ps[1]);
-  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_GRID(N), a.ps[1], a.kap, a.tth, P, a.ps[2]);
-  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_GRID(N), a.ps[2], a.kap, a.tth, P, a.ps[3]);
-  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_GRID(N), a.ps[3], a.kap, a.tth, P, a.ps[4]);
+  hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N, B), a.yh, a.phip, a.z, d.prm, a.kap, a.tth);
+  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_GRID(N, B), a.rs[0], a.s, d.prm, a.rs[1]);
+  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_GRID(N, B), a.rs[1], a.s, d.prm, a.rs[2]);
+  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_GRID(N, B), a.rs[2], a.s, d.prm, a.rs[3]);
+  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_GRID(N, B), a.rs[3], a.s, d.prm, a.rs[4]);
+  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_GRID(N, B), a.phip, a.kap, a.tth, d.prm, a.ps[1]);
+  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_GRID(N, B), a.ps[1], a.kap, a.tth, d.prm, a.ps[2]);
+  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_GRID(N, B), a.ps[2], a.kap, a.tth, d.prm, a.ps[3]);
+  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_GRID(N, B), a.ps[3], a.kap, a.tth, d.prm, a.ps[4]);
   return hipGetLastError();
 }
-hipError_t g_launch_loss_bar(const float* phi, const float* ptrue, const GradFwd& a, float dmean, float inv_nL,
-                             float* pbar, hipStream_t st) {
-  const GradPrm P = a.prm;
-  hipLaunchKernelGGL(k_g_loss_bar, DDH_G_GRID(P.N), phi, ptrue, P, dmean, inv_nL, pbar);
+hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d, int N, int B, float* pbar,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_g_dsum, DDH_G_GRID(N, B), phi, ptrue, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_combine<G_LOSS>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.scal, d.loss,
+                     d.tot, d.flag);
+  hipLaunchKernelGGL(k_g_loss_bar, DDH_G_GRID(N, B), phi, ptrue, d.prm, d.loss, pbar);
   return hipGetLastError();
 }
-// frame reversed up to the tip/tilt adjoint sums: leaves rbar = adjoint of the
-// frame's input r, pb2 = adjoint of phi' (before the plane projection)
-hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, hipStream_t st) {
-  const GradPrm P = a.prm;
-  const int N = P.N;
+// frame reversed: pbar (adjoint of the frame's output phase) becomes the
+// adjoint of its input phase, rbar likewise for r; gs2, gsr, gbeta accumulate
+hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st) {
+  const long long n = (long long)B * N * N;
+  hipError_t e = launch_fill_zero(g.kbar, n, st);
+  if (e == hipSuccess) e = launch_fill_zero(g.tbar, n, st);
+  if (e == hipSuccess) e = launch_fill_zero(g.sbar, n, st);
+  if (e != hipSuccess) return e;
   // phi sweep reversed (ps[c] = input of pass c, ps[0] = phi')
   const float* ps0 = a.phip;
-#define DDH_PB(C)                                                                                                  \
-  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_GRID(N), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, P, g.pbar, \
-                     g.em, g.kbar, g.tbar, g.gbeta);                                                              \
-  hipLaunchKernelGGL(k_g_pback_b, DDH_G_GRID(N), g.em, P, g.pbar);
+#define DDH_PB(C)                                                                                        \
+  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_GRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, \
+                     d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta);                                       \
+  hipLaunchKernelGGL(k_g_pback_b, DDH_G_GRID(N, B), g.em, d.prm, g.pbar);
   DDH_PB(3) DDH_PB(2) DDH_PB(1) DDH_PB(0)
 #undef DDH_PB
-  hipError_t e = launch_copy(g.pb2, g.pbar, (long long)N * N, st);
+  e = launch_copy(g.pb2, g.pbar, n, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, P, g.pb2, g.zbar, g.gs2);
+  hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, d.prm, g.pb2, g.zbar,
+                     g.gs2);
   // r sweep reversed (rs[c] = input of pass c)
-#define DDH_RB(C)                                                                                             \
-  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_GRID(N), a.rs[C], a.rs[C + 1], a.s, P, g.rbar, g.sbar, g.Abar, g.Bbar, \
-                     g.gsr);                                                                                 \
-  hipLaunchKernelGGL(k_g_rback_b<C>, DDH_G_GRID(N), a.rs[C], g.Abar, g.Bbar, P, g.rbar);
+#define DDH_RB(C)                                                                                               \
+  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_GRID(N, B), a.rs[C], a.rs[C + 1], a.s, d.prm, g.rbar, g.sbar, g.Abar, \
+                     g.Bbar, g.gsr);                                                                           \
+  hipLaunchKernelGGL(k_g_rback_b<C>, DDH_G_GRID(N, B), a.rs[C], g.Abar, g.Bbar, d.prm, g.rbar);
   DDH_RB(3) DDH_RB(2) DDH_RB(1) DDH_RB(0)
 #undef DDH_RB
   // z = F mu  ->  mubar = F^H zbar
-  e = launch_fft2(N, 1, g.zbar, g.mubar, a.work, a.tw, 1, st);
+  e = launch_fft2(N, B, g.zbar, g.mubar, a.work, a.tw, 1, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_estep_bar, DDH_G_GRID(N), a.r_in, a.b, a.rs[0], g.mubar, g.sbar, P, g.rbar, g.bbar, g.gs2);
+  hipLaunchKernelGGL(k_g_estep_bar, DDH_G_GRID(N, B), a.r_in, a.b, a.rs[0], g.mubar, g.sbar, d.prm, g.rbar, g.bbar,
+                     g.gs2);
   // b = F^H v  ->  vbar = F bbar
-  e = launch_fft2(N, 1, g.bbar, g.vbar, a.work, a.tw, 0, st);
+  e = launch_fft2(N, B, g.bbar, g.vbar, a.work, a.tw, 0, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_bp_bar, DDH_G_GRID(N), g.vbar, a.yh, a.phip, P, g.pb2);
+  hipLaunchKernelGGL(k_g_bp_bar, DDH_G_GRID(N, B), g.vbar, a.yh, a.phip, d.prm, g.pb2);
+  // tip/tilt removal reversed: the plane of pb2 over the pupil, subtracted
+  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N, B), g.pb2, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_combine<G_PLANE>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.bscal, d.loss,
+                     d.tot, d.flag);
+  hipLaunchKernelGGL(k_g_plane_bar, DDH_G_GRID(N, B), g.pb2, d.prm, d.bscal, g.pbar);
   return hipGetLastError();
 }
-hipError_t g_launch_plane_bar(const float* pb2, const GradFwd& a, const float* coef, float* pbar, hipStream_t st) {
-  const GradPrm P = a.prm;
-  GradScal S{0.f, 0.f, 0.f, coef[0], coef[1], coef[2]};
-  hipLaunchKernelGGL(k_g_plane_bar, DDH_G_GRID(P.N), pb2, P, S, pbar);
+hipError_t g_launch_totals(const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_g_tsum, DDH_G_GRID(N, B), g.gs2, g.gsr, g.gbeta, N, d.part);
+  hipLaunchKernelGGL(k_g_combine<G_TOTAL>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.scal, d.loss,
+                     d.tot, d.flag);
   return hipGetLastError();
 }
 #undef DDH_G_GRID

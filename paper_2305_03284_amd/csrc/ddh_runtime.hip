@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -1100,56 +1101,68 @@ int ddh_fft2(int N, int count, const void* in, void* out, void* work, int invers
 
 
 // ------------------------------------------------------- differentiation
-int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const float* phi0, const float* phi_true,
-                      int ckpt, float* d_phi0, ddh_grad_out* out, void* hip_stream) {
-  if (!p || !y || !phi0 || !phi_true || !d_phi0 || !out || K < 1 || ckpt < 1) return DDH_EINVAL;
-  int rc = validate(p);
-  if (rc != DDH_OK) return rc;
-  if (p->n_k != 1 || !(p->qg_p == 2.0f)) return DDH_EINVAL;
-  for (int k = 0; k < K; ++k)
-    if (!y[k]) return DDH_EINVAL;
+int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* const* y, const float* const* phi0,
+                            const float* const* phi_true, int ckpt, float* const* d_phi0, ddh_grad_out* out,
+                            void* hip_stream) {
+  if (!p || !y || !phi0 || !phi_true || !d_phi0 || !out || count < 1 || K < 1 || ckpt < 1) return DDH_EINVAL;
+  const int N = p[0].N;
+  for (int b = 0; b < count; ++b) {
+    const int rc = validate(&p[b]);
+    if (rc != DDH_OK) return rc;
+    if (p[b].n_k != 1 || !(p[b].qg_p == 2.0f) || p[b].N != N) return DDH_EINVAL;
+    if (!phi0[b] || !phi_true[b] || !d_phi0[b]) return DDH_EINVAL;
+    for (int k = 0; k < K; ++k)
+      if (!y[(size_t)b * K + k]) return DDH_EINVAL;
+  }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int dev = 0;
   DDH_CHECK(hipGetDevice(&dev));
   float2* tw_all = nullptr;
-  rc = ensure_twiddles(dev, &tw_all);
+  int rc = ensure_twiddles(dev, &tw_all);
   if (rc != DDH_OK) return rc;
-  const int N = p->N;
-  const size_t px = (size_t)N * N;
+  const int B = count;
+  const size_t px = (size_t)N * N, bpx = (size_t)B * px;
+  if (bpx > (size_t)INT32_MAX) return DDH_EINVAL;  // pixel indices of a batch are 32-bit
   const int nb = (int)((px + 255) / 256);
-  GradPrm P{};
-  P.N = N;
-  P.d2 = p->pupil_diameter * p->pupil_diameter;
-  P.lam = p->lambda;
-  P.alpha = p->alpha;
-  P.fl = p->r_floor;
-  P.s2 = p->sigma_w2;
-  P.inv_sp = (float)(1.0 / ((double)p->qg_sigma * (double)p->qg_sigma));
-  P.pmq = p->qg_p - p->qg_q;
-  P.lc = (float)(((double)p->qg_p - (double)p->qg_q) * std::log2(1.0 / ((double)p->qg_T * (double)p->qg_sigma)));
-  P.qop = p->qg_q / p->qg_p;
-  P.beta = p->beta_phi;
-  P.sig_r = p->qg_sigma;
-  // inverse of the pupil moment matrix (plane fit)
-  double minv[6];
-  {
+  // per-stream constants and the inverse of each pupil's moment matrix (plane fit)
+  std::vector<GradPrm> prm(B);
+  std::vector<double> minv(6 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    const ddh_params& q = p[b];
+    GradPrm& P = prm[b];
+    P.N = N;
+    P.d2 = q.pupil_diameter * q.pupil_diameter;
+    P.lam = q.lambda;
+    P.alpha = q.alpha;
+    P.fl = q.r_floor;
+    P.s2 = q.sigma_w2;
+    P.inv_sp = (float)(1.0 / ((double)q.qg_sigma * (double)q.qg_sigma));
+    P.pmq = q.qg_p - q.qg_q;
+    P.lc = (float)(((double)q.qg_p - (double)q.qg_q) * std::log2(1.0 / ((double)q.qg_T * (double)q.qg_sigma)));
+    P.qop = q.qg_q / q.qg_p;
+    P.beta = q.beta_phi;
+    P.sig_r = q.qg_sigma;
     double m[6] = {0, 0, 0, 0, 0, 0};
     const double c = 0.5 * (N - 1);
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) {
         const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
         if ((float)(di * di + dj * dj) > P.d2) continue;
-        const double a = i - c, b = j - c;
-        m[0] += 1, m[1] += a, m[2] += b, m[3] += a * a, m[4] += a * b, m[5] += b * b;
+        const double a = i - c, e = j - c;
+        m[0] += 1, m[1] += a, m[2] += e, m[3] += a * a, m[4] += a * e, m[5] += e * e;
       }
     const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
     const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
     const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
     const double det = a00 * c00 + a01 * c01 + a02 * c02;
     const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
-    for (int q = 0; q < 6; ++q) minv[q] = det != 0.0 ? inv[q] : 0.0;
+    for (int k = 0; k < 6; ++k) minv[6 * (size_t)b + k] = det != 0.0 ? inv[k] : 0.0;
   }
-  // ---- workspace: checkpoints, one segment of frame stashes, adjoint arrays
+  // frame tables, frame-major: ytab[k * B + b]
+  std::vector<const void*> ytab((size_t)K * B);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < K; ++k) ytab[(size_t)k * B + b] = y[(size_t)b * K + k];
+  // ---- workspace: checkpoints, one segment of frame stashes, adjoint arrays, scalars
   const int nseg = (K + ckpt - 1) / ckpt;
   const int per_frame_f = 4 + 5 + 4;  // phip s kap tth | rs[0..4] | ps[1..4]
   const int per_frame_c = 5;          // yh v b mu z
@@ -1159,149 +1172,149 @@ int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const fl
     off = align256(off + bytes);
     return o;
   };
-  const size_t o_ck = take(2 * (size_t)nseg * px * 4);
-  const size_t o_st = take((size_t)ckpt * (per_frame_f * px * 4 + per_frame_c * px * 8));
-  const size_t o_work = take(px * 8);
-  const size_t o_r0 = take(px * 4);
-  const size_t o_bf = take(15 * px * 4);
-  const size_t o_bc = take(4 * px * 8);
-  const size_t o_part = take((size_t)nb * 3 * 8);
+  const size_t o_ck = take(2 * (size_t)nseg * bpx * 4);
+  const size_t o_st = take((size_t)ckpt * (per_frame_f * bpx * 4 + per_frame_c * bpx * 8));
+  const size_t o_work = take(bpx * 8);
+  const size_t o_r0 = take(bpx * 4);
+  const size_t o_in = take(2 * bpx * 4);  // phi0 and phi_true of every stream, batched
+  const size_t o_bf = take(12 * bpx * 4);
+  const size_t o_bc = take(4 * bpx * 8);
+  const size_t o_part = take((size_t)B * nb * 3 * 8);
+  const size_t o_prm = take(sizeof(GradPrm) * B);
+  const size_t o_minv = take(sizeof(double) * 6 * B);
+  const size_t o_scal = take(2 * sizeof(GradScal) * B);
+  const size_t o_loss = take(sizeof(GradLoss) * B);
+  const size_t o_tot = take(sizeof(double) * 3 * B);
+  const size_t o_flag = take(sizeof(int) * B);
+  const size_t o_ytab = take(sizeof(void*) * (size_t)K * B);
   char* mem = nullptr;
   hipError_t e = hipMalloc(&mem, off);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(grad)");
-  std::vector<double> part(nb * 3);
-  auto sums = [&](double (&x)[3]) -> int {
-    DDH_CHECK(hipMemcpyAsync(part.data(), mem + o_part, sizeof(double) * nb * 3, hipMemcpyDeviceToHost, st));
-    DDH_CHECK(hipStreamSynchronize(st));
-    x[0] = x[1] = x[2] = 0.0;
-    for (int b = 0; b < nb; ++b)
-      for (int q = 0; q < 3; ++q) x[q] += part[b * 3 + q];
-    return DDH_OK;
+  auto fail = [&](int code) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    return code;
   };
-  double* dpart = (double*)(mem + o_part);
+  GradDev dv{};
+  dv.prm = (const GradPrm*)(mem + o_prm);
+  dv.minv = (const double*)(mem + o_minv);
+  dv.scal = (GradScal*)(mem + o_scal);
+  dv.bscal = dv.scal + B;
+  dv.loss = (GradLoss*)(mem + o_loss);
+  dv.tot = (double*)(mem + o_tot);
+  dv.flag = (int*)(mem + o_flag);
+  dv.part = (double*)(mem + o_part);
+  const float2* const* dytab = (const float2* const*)(mem + o_ytab);
+  if (hipMemcpyAsync(mem + o_prm, prm.data(), sizeof(GradPrm) * B, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(mem + o_minv, minv.data(), sizeof(double) * 6 * B, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(mem + o_ytab, ytab.data(), sizeof(void*) * ytab.size(), hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+    return fail(DDH_EDEVICE);
   float* ck = (float*)(mem + o_ck);
-  auto ck_r = [&](int sgi) { return ck + (size_t)(2 * sgi) * px; };
-  auto ck_p = [&](int sgi) { return ck + (size_t)(2 * sgi + 1) * px; };
+  auto ck_r = [&](int sgi) { return ck + (size_t)(2 * sgi) * bpx; };
+  auto ck_p = [&](int sgi) { return ck + (size_t)(2 * sgi + 1) * bpx; };
   std::vector<GradFwd> slot(ckpt);
   {
     char* q = mem + o_st;
     for (int t = 0; t < ckpt; ++t) {
       GradFwd& a = slot[t];
       float* fb = (float*)q;
-      a.phip = fb, a.s = fb + px, a.kap = fb + 2 * px, a.tth = fb + 3 * px;
-      for (int c = 0; c < 5; ++c) a.rs[c] = fb + (4 + c) * px;
+      a.phip = fb, a.s = fb + bpx, a.kap = fb + 2 * bpx, a.tth = fb + 3 * bpx;
+      for (int c = 0; c < 5; ++c) a.rs[c] = fb + (4 + c) * bpx;
       a.ps[0] = nullptr;
-      for (int c = 1; c < 5; ++c) a.ps[c] = fb + (8 + c) * px;
-      float2* cb = (float2*)(q + per_frame_f * px * 4);
-      a.yh = cb, a.v = cb + px, a.b = cb + 2 * px, a.mu = cb + 3 * px, a.z = cb + 4 * px;
+      for (int c = 1; c < 5; ++c) a.ps[c] = fb + (8 + c) * bpx;
+      float2* cb = (float2*)(q + per_frame_f * bpx * 4);
+      a.yh = cb, a.v = cb + bpx, a.b = cb + 2 * bpx, a.mu = cb + 3 * bpx, a.z = cb + 4 * bpx;
       a.work = (float2*)(mem + o_work);
       a.tw = tw_all + twiddle_offset(N);
-      a.prm = P;
-      q += per_frame_f * px * 4 + per_frame_c * px * 8;
+      q += per_frame_f * bpx * 4 + per_frame_c * bpx * 8;
     }
   }
   float* rzero = (float*)(mem + o_r0);
+  float* pin = (float*)(mem + o_in);
+  float* ptrue = pin + bpx;
   GradBwd g{};
   {
     float* f = (float*)(mem + o_bf);
-    float** fp[15] = {&g.rbar, &g.pbar, &g.pb2, &g.em, &g.kbar, &g.tbar, &g.sbar, &g.Abar, &g.Bbar,
-                      &g.gs2, &g.gsr, &g.gbeta, nullptr, nullptr, nullptr};
-    for (int q = 0; q < 12; ++q) *fp[q] = f + q * px;
+    float** fp[12] = {&g.rbar, &g.pbar, &g.pb2, &g.em, &g.kbar, &g.tbar, &g.sbar, &g.Abar, &g.Bbar,
+                      &g.gs2, &g.gsr, &g.gbeta};
+    for (int q = 0; q < 12; ++q) *fp[q] = f + q * bpx;
     float2* c = (float2*)(mem + o_bc);
-    g.zbar = c, g.mubar = c + px, g.bbar = c + 2 * px, g.vbar = c + 3 * px;
+    g.zbar = c, g.mubar = c + bpx, g.bbar = c + 2 * bpx, g.vbar = c + 3 * bpx;
   }
-  auto fail = [&](int code) {
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(mem);
-    return code;
-  };
-  auto zero = [&](float* x, size_t n) { return launch_fill_zero(x, (long long)n, st); };
-  if (zero(rzero, px) != hipSuccess || zero((float*)(mem + o_bf), 15 * px) != hipSuccess)
+  if (launch_fill_zero(rzero, (long long)bpx, st) != hipSuccess ||
+      launch_fill_zero((float*)(mem + o_bf), 12 * (long long)bpx, st) != hipSuccess ||
+      launch_fill_zero((float*)dv.flag, B, st) != hipSuccess)
     return fail(DDH_EDEVICE);
+  for (int b = 0; b < B; ++b)
+    if (launch_copy(pin + b * px, phi0[b], (long long)px, st) != hipSuccess ||
+        launch_copy(ptrue + b * px, phi_true[b], (long long)px, st) != hipSuccess)
+      return fail(DDH_EDEVICE);
   // one frame forward into slot t from (r_in, phi_in)
-  auto frame = [&](int k, int t, const float* r_in, const float* phi_in) -> int {
+  auto frame = [&](int k, int t, const float* r_in, const float* phi_in) -> bool {
     GradFwd& a = slot[t];
-    a.y = static_cast<const float2*>(y[k]);
+    a.y = dytab + (size_t)k * B;
     a.r_in = r_in;
     a.phi_in = phi_in;
-    double x[3];
-    if (g_launch_ysum(a.y, N, dpart, st) != hipSuccess) return DDH_EDEVICE;
-    if (sums(x) != DDH_OK) return DDH_EDEVICE;
-    const double mr = x[0] / px, mi = x[1] / px;
-    const double m2 = x[2] - (double)px * (mr * mr + mi * mi);
-    if (!(m2 > 0.0) || !std::isfinite(m2)) return DDH_EDATA;
-    if (g_launch_psum(phi_in, N, P.d2, dpart, st) != hipSuccess) return DDH_EDEVICE;
-    if (sums(x) != DDH_OK) return DDH_EDEVICE;
-    a.scal = GradScal{(float)mr, (float)mi, (float)std::sqrt((double)px / m2),
-                      (float)(minv[0] * x[0] + minv[1] * x[1] + minv[2] * x[2]),
-                      (float)(minv[1] * x[0] + minv[3] * x[1] + minv[4] * x[2]),
-                      (float)(minv[2] * x[0] + minv[4] * x[1] + minv[5] * x[2])};
-    return g_launch_forward(a, st) == hipSuccess ? DDH_OK : DDH_EDEVICE;
+    return g_launch_forward(a, dv, N, B, st) == hipSuccess;
   };
   // ---- forward with checkpoints
   const float* r_cur = rzero;
-  const float* p_cur = phi0;
+  const float* p_cur = pin;
   for (int k = 0; k < K; ++k) {
     if (k % ckpt == 0) {
-      if (launch_copy(ck_r(k / ckpt), r_cur, (long long)px, st) != hipSuccess ||
-          launch_copy(ck_p(k / ckpt), p_cur, (long long)px, st) != hipSuccess)
+      if (launch_copy(ck_r(k / ckpt), r_cur, (long long)bpx, st) != hipSuccess ||
+          launch_copy(ck_p(k / ckpt), p_cur, (long long)bpx, st) != hipSuccess)
         return fail(DDH_EDEVICE);
       r_cur = ck_r(k / ckpt);
       p_cur = ck_p(k / ckpt);
     }
     const int t = k % ckpt;
-    rc = frame(k, t, r_cur, p_cur);
-    if (rc != DDH_OK) return fail(rc);
+    if (!frame(k, t, r_cur, p_cur)) return fail(DDH_EDEVICE);
     r_cur = slot[t].rs[4];
     p_cur = slot[t].ps[4];
   }
-  // ---- loss on the last phase
-  double x[3];
-  if (g_launch_dsum(p_cur, phi_true, N, P.d2, dpart, st) != hipSuccess || sums(x) != DDH_OK)
-    return fail(DDH_EDEVICE);
-  const double n = x[2], dmean = x[0] / n, var = x[1] / n - dmean * dmean;
-  const double L = std::sqrt(std::max(var, 0.0));
-  out->loss = L;
-  if (!(L > 0.0)) return fail(DDH_EDATA);
-  if (g_launch_loss_bar(p_cur, phi_true, slot[(K - 1) % ckpt], (float)dmean, (float)(1.0 / (n * L)), g.pbar, st) !=
-      hipSuccess)
-    return fail(DDH_EDEVICE);
+  // ---- loss on the last phase and its adjoint
+  if (g_launch_loss(p_cur, ptrue, dv, N, B, g.pbar, st) != hipSuccess) return fail(DDH_EDEVICE);
   // ---- backward, segment by segment (recomputing each segment's stashes)
   for (int sgi = nseg - 1; sgi >= 0; --sgi) {
     const int k0 = sgi * ckpt, k1 = std::min(K, k0 + ckpt);
     const float* rr = ck_r(sgi);
     const float* pp = ck_p(sgi);
     for (int k = k0; k < k1; ++k) {
-      rc = frame(k, k - k0, rr, pp);
-      if (rc != DDH_OK) return fail(rc);
+      if (!frame(k, k - k0, rr, pp)) return fail(DDH_EDEVICE);
       rr = slot[k - k0].rs[4];
       pp = slot[k - k0].ps[4];
     }
-    for (int k = k1 - 1; k >= k0; --k) {
-      const GradFwd& a = slot[k - k0];
-      if (zero(g.kbar, px) != hipSuccess || zero(g.tbar, px) != hipSuccess || zero(g.sbar, px) != hipSuccess)
-        return fail(DDH_EDEVICE);
-      if (g_launch_backward(a, g, st) != hipSuccess) return fail(DDH_EDEVICE);
-      if (g_launch_psum(g.pb2, N, P.d2, dpart, st) != hipSuccess || sums(x) != DDH_OK) return fail(DDH_EDEVICE);
-      const float coef[3] = {(float)(minv[0] * x[0] + minv[1] * x[1] + minv[2] * x[2]),
-                             (float)(minv[1] * x[0] + minv[3] * x[1] + minv[4] * x[2]),
-                             (float)(minv[2] * x[0] + minv[4] * x[1] + minv[5] * x[2])};
-      if (g_launch_plane_bar(g.pb2, a, coef, g.pbar, st) != hipSuccess) return fail(DDH_EDEVICE);
-    }
+    for (int k = k1 - 1; k >= k0; --k)
+      if (g_launch_backward(slot[k - k0], g, dv, N, B, st) != hipSuccess) return fail(DDH_EDEVICE);
   }
   // ---- outputs
-  if (launch_copy(d_phi0, g.pbar, (long long)px, st) != hipSuccess) return fail(DDH_EDEVICE);
-  const float big = 1e30f;
-  double gsum[3];
-  float* acc[3] = {g.gs2, g.gsr, g.gbeta};
-  for (int q = 0; q < 3; ++q) {
-    if (g_launch_psum(acc[q], N, big, dpart, st) != hipSuccess || sums(x) != DDH_OK) return fail(DDH_EDEVICE);
-    gsum[q] = x[0];
+  if (g_launch_totals(g, dv, N, B, st) != hipSuccess) return fail(DDH_EDEVICE);
+  for (int b = 0; b < B; ++b)
+    if (launch_copy(d_phi0[b], g.pbar + b * px, (long long)px, st) != hipSuccess) return fail(DDH_EDEVICE);
+  std::vector<GradLoss> lo(B);
+  std::vector<double> tot(3 * (size_t)B);
+  std::vector<int> flag(B);
+  if (hipMemcpyAsync(lo.data(), dv.loss, sizeof(GradLoss) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(tot.data(), dv.tot, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(flag.data(), dv.flag, sizeof(int) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(DDH_EDEVICE);
+  int res = DDH_OK;
+  for (int b = 0; b < B; ++b) {
+    out[b].loss = lo[b].loss;
+    out[b].d_sigma_w = 2.0 * std::sqrt((double)p[b].sigma_w2) * tot[3 * b];
+    out[b].d_sigma_r = tot[3 * b + 1];
+    out[b].d_beta = tot[3 * b + 2];
+    if (flag[b]) res = DDH_EDATA;
   }
-  out->d_sigma_w = 2.0 * std::sqrt((double)p->sigma_w2) * gsum[0];
-  out->d_sigma_r = gsum[1];
-  out->d_beta = gsum[2];
-  return fail(DDH_OK);
+  return fail(res);
+}
+
+int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const float* phi0, const float* phi_true,
+                      int ckpt, float* d_phi0, ddh_grad_out* out, void* hip_stream) {
+  return ddh_unrolled_grad_batch(p, 1, K, y, &phi0, &phi_true, ckpt, &d_phi0, out, hip_stream);
 }
 
 }  // extern "C"
