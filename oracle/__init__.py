@@ -20,6 +20,13 @@ Parity status of each function (what pins it):
                                 conjugate conventions of A_phi, A_phi^H, theta)
   em / ddh_frame .............. cost_U non-increasing over 200 iterations;
                                 piston invariance; integer-tilt = image shift
+  dh_mbir ..................... EM from r = 0 stays at the floor (the loop
+                                needs its reset); a lambda = 1 reset makes the
+                                result independent of r0; U non-increasing
+                                between resets
+  grad.reference_gradient ..... loss equals ddh's to 1e-12; FP64 central
+                                differences of ddh's loss (sigma_w, sigma_r,
+                                beta, a direction in phi0)
   cost_U ...................... dense Gaussian likelihood at N=8, a=1
   strehl ...................... S=1 for constant / tilt residual, Marechal
 """

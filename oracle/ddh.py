@@ -355,6 +355,32 @@ def ddh_frame(r, phi, y, a, prm: Params, trace: list | None = None):
     return r, phi
 
 
+def dh_mbir(y, a, prm: Params, iters: int, reset_every: int, r0=None, phi0=None):
+    """Conventional single-shot DH-MBIR with periodic bootstrap resets (the
+    DH-MBIR Algorithm section: hundreds of EM iterations on one frame, with r
+    reset to a back-projected estimate every 200 iterations).
+
+    Reading: the reset is the Eq. (3) initialisation, whose second term is
+    the bootstrap's |back-projection|^2 estimate, applied with the stream's
+    lambda (lambda = 1 discards the previous r, as the bootstrap does), on the
+    frame prologue (Normalize, RemoveTipTilt); it is followed by one EM
+    iteration.  Iteration it (0-based) is such a reset when it % reset_every
+    == 0, and otherwise one plain EM(r, phi; y).  Starts from r = phi = 0
+    unless r0 / phi0 are given."""
+    if iters < 0 or reset_every < 1:
+        raise ValueError("iters >= 0 and reset_every >= 1")
+    N = a.shape[0]
+    r = np.zeros((N, N)) if r0 is None else np.array(r0, dtype=np.float64)
+    phi = np.zeros((N, N)) if phi0 is None else np.array(phi0, dtype=np.float64)
+    one = dataclasses.replace(prm, n_k=1)
+    for it in range(iters):
+        if it % reset_every == 0:
+            r, phi = ddh_frame(r, phi, y, a, one)
+        else:
+            r, phi = em(r, phi, y, a, one)
+    return r, phi
+
+
 def run_stream(frames, a, prm: Params, r0=None, phi0=None):
     """DDH_MBIR over a sequence of frames starting from r = 0, phi = 0
     (Fig. 1); yields (r, phi) after each frame."""

@@ -567,3 +567,64 @@ def test_reference_gradient_against_central_differences():
     fd = (G.oracle_loss(phi0 + h * d, sw, sr, bt, frames, ptrue, a, prm)
           - G.oracle_loss(phi0 - h * d, sw, sr, bt, frames, ptrue, a, prm)) / (2 * h)
     assert abs(fd - np.sum(g0 * d)) <= 2e-3 * abs(fd)
+
+
+def _mbir_case(N=16):
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=5, stream_id=0))
+    return st, ddh.aperture(N), st.frame(0).astype(np.complex128)
+
+
+def test_plain_loop_without_bootstrap_stays_at_r_zero():
+    """r = 0 is a fixed point of EM up to the floor (w = 0, so s = 0 and the
+    cubic's root is 0): twenty plain EM iterations from r = 0 leave r within
+    0.1 % of the floor, which is why the conventional loop starts with a
+    reset.  Zero iterations return the start state."""
+    st, a, y = _mbir_case()
+    prm = ddh.Params(sigma_w2=st.sigma_w2)
+    r, phi = np.zeros((16, 16)), np.zeros((16, 16))
+    for _ in range(20):
+        r, phi = ddh.em(r, phi, y, a, prm)
+    assert r.max() < 1.001 * prm.r_floor
+    assert np.abs(phi).max() < 1e-6
+    r, phi = ddh.dh_mbir(y, a, prm, iters=0, reset_every=1, r0=np.ones((16, 16)), phi0=np.full((16, 16), 0.5))
+    assert np.all(r == 1.0) and np.all(phi == 0.5)
+    r, _ = ddh.dh_mbir(y, a, prm, iters=1, reset_every=1)
+    assert r.max() > 1e3 * prm.r_floor
+
+
+def test_full_bootstrap_reset_discards_the_previous_r():
+    """With lambda = 1 a reset replaces r by the back-projection estimate, so
+    the result of a run that starts with a reset does not depend on r0; with
+    lambda < 1 it does."""
+    import dataclasses
+    st, a, y = _mbir_case()
+    rng = np.random.default_rng(3)
+    phi0 = 0.2 * rng.standard_normal((16, 16))
+    full = dataclasses.replace(ddh.Params(sigma_w2=st.sigma_w2), lam=1.0)
+    outs = [ddh.dh_mbir(y, a, full, iters=7, reset_every=3, r0=r0, phi0=phi0)
+            for r0 in (np.zeros((16, 16)), rng.uniform(0.1, 2.0, (16, 16)))]
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    part = dataclasses.replace(full, lam=0.45)
+    outs = [ddh.dh_mbir(y, a, part, iters=2, reset_every=3, r0=r0, phi0=phi0)
+            for r0 in (np.zeros((16, 16)), np.ones((16, 16)))]
+    assert not np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_conventional_loop_cost_decreases_between_resets():
+    """Between two resets the iterations are plain EM steps, each of which
+    does not increase the MAP surrogate cost U."""
+    import dataclasses
+    from oracle import metrics as M
+    st, a, y = _mbir_case()
+    prm = dataclasses.replace(ddh.Params(sigma_w2=st.sigma_w2), lam=1.0)
+    yh = ddh.normalize(y)
+    r, phi = ddh.dh_mbir(y, a, prm, iters=1, reset_every=50)
+    U = [M.cost_U(r, phi, yh, a, prm)]
+    for _ in range(10):
+        r, phi = ddh.em(r, phi, y, a, prm)
+        U.append(M.cost_U(r, phi, yh, a, prm))
+    r2, phi2 = ddh.dh_mbir(y, a, prm, iters=11, reset_every=50)
+    np.testing.assert_array_equal(r2, r)
+    np.testing.assert_array_equal(phi2, phi)
+    assert np.all(np.diff(U) <= 1e-12 * np.abs(U[1:]))
