@@ -104,6 +104,20 @@ int ddh_step(ddh_stream_t s, const void* y, void* hip_stream);
  * RemoveTipTilt and no Eq. (3) initialisation.  Same y contract as ddh_step. */
 int ddh_em(ddh_stream_t s, const void* y, void* hip_stream);
 
+/* Conventional single-shot DH-MBIR (DH-MBIR section): `iters` EM iterations
+ * on the one frame y, with a bootstrap reset of r every `reset_every`
+ * iterations (the paper's bootstrap resets every 200).  Iteration it
+ * (0-based) with it % reset_every == 0 is a reset: the frame prologue
+ * (Normalize, RemoveTipTilt), the Eq. (3) initialisation r = (1 - lambda) r
+ * + lambda alpha |b|^2 with the stream's lambda (a stream made with lambda = 1
+ * replaces r by the back-projection estimate, as the bootstrap does), then one
+ * EM iteration; every other iteration is ddh_em.  The stream's n_k is not
+ * used.  Continues from the stream's state (set r = phi = 0 with
+ * ddh_set_state for the paper's cold start); the frame count grows by one.
+ * Eager launches on hip_stream; same y contract as ddh_step.  DDH_EINVAL for
+ * iters < 0 or reset_every < 1. */
+int ddh_mbir(ddh_stream_t s, const void* y, int iters, int reset_every, void* hip_stream);
+
 /* WriteData (Fig. 1): copy the current phase phi (radians, unwrapped, zero
  * off the pupil) or reflectance r (Normalize units) into out, a device
  * pointer to N*N floats, on hip_stream.  Synchronise before reading. */

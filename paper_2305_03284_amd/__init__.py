@@ -46,6 +46,7 @@ SIGNATURES = {
     "ddh_destroy_stream": (_c_int, [_c_void_p]),
     "ddh_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
     "ddh_em": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "ddh_mbir": (_c_int, [_c_void_p, _c_void_p, _c_int, _c_int, _c_void_p]),
     "ddh_get_phase": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
     "ddh_get_reflectance": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
     "ddh_set_state": (_c_int, [_c_void_p, _c_void_p, _c_void_p, _c_ll, _c_void_p]),
@@ -171,6 +172,13 @@ class Stream:
         """One plain EM(r, phi; y) iteration."""
         _check_frame(y, self.N)
         _check(lib().ddh_em(self.handle, ctypes.c_void_p(y.data_ptr()), _stream_ptr()), "ddh_em")
+
+    def mbir(self, y, iters: int, reset_every: int = 200) -> None:
+        """Conventional DH-MBIR on one frame: iters EM iterations with a
+        bootstrap reset every reset_every iterations (ddh_mbir)."""
+        _check_frame(y, self.N)
+        _check(lib().ddh_mbir(self.handle, ctypes.c_void_p(y.data_ptr()), int(iters), int(reset_every),
+                              _stream_ptr()), "ddh_mbir")
 
     def phase(self):
         torch = _torch()

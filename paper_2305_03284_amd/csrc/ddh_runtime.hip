@@ -530,6 +530,25 @@ int ddh_em(ddh_stream_t s, const void* y, void* hip_stream) {
   return single_step(s, y, static_cast<hipStream_t>(hip_stream), 0);
 }
 
+int ddh_mbir(ddh_stream_t s, const void* y, int iters, int reset_every, void* hip_stream) {
+  int rc = check_stream(s);
+  if (rc != DDH_OK) return rc;
+  if (!y || iters < 0 || reset_every < 1) return DDH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const float2* yp = static_cast<const float2*>(y);
+  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
+  for (int it = 0; it < iters; ++it) {
+    // a reset is the frame prologue with Eq. (3) and one EM iteration; the
+    // other iterations are plain EM
+    const int mode = it % reset_every == 0 ? 1 : 0;
+    rc = enqueue_frame(s->dptr, g, 1, 1, mode, st, NoTiming{}, &yp, &s->parity);
+    if (rc != DDH_OK) return rc;
+    s->parity ^= 1;
+  }
+  if (iters > 0) s->n++;
+  return DDH_OK;
+}
+
 static int copy_state(ddh_stream_t s, float* out, bool phase, hipStream_t st) {
   const float* src = phase ? s->h.phi[s->parity] : s->h.r[s->parity];
   DDH_CHECK(hipMemcpyAsync(out, src, sizeof(float) * (size_t)s->N * s->N, hipMemcpyDeviceToDevice, st));

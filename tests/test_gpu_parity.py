@@ -254,6 +254,81 @@ def test_two_em_iterations_per_frame_and_smaller_pupil():
         compare(f"frame {n}", *state(s), r_o, p_o, a)
 
 
+def test_conventional_dh_mbir_with_bootstrap_resets():
+    """Conventional single-shot DH-MBIR (ddh_mbir), 50 EM iterations on one
+    frame with a full (lambda = 1) bootstrap reset every 20, from r = phi = 0.
+
+    * The loop's schedule: bit for bit the same as the explicit sequence of
+      single calls (a one-iteration ddh_mbir is a reset, ddh_em a plain step).
+    * Every iteration against the oracle's iteration from the same (float32)
+      state (teacher forcing).  Free-running chains are not compared element
+      by element: the cubic's choice among its roots is a floating-point
+      decision, and at a near-tie FP32 and FP64 pick different roots at a
+      pixel (measured: 1e-6 agreement right after each reset, a jump of 2e-2
+      at one pixel by iteration 50), after which the chains part.
+    * The free-running end state's Strehl against the oracle's within 0.005."""
+    torch = _torch()
+    D = _ddh()
+    N = 64
+    st = synth.config0_stream()
+    prm, gp = make_pair(N, st.sigma_w2, lam=1.0)
+    a = O.aperture(N)
+    y = st.frame(0)
+    yc, yd = y.astype(np.complex128), dev(y)
+    z = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s = D.Stream(N, gp)
+    s.set_state(z, z, 0)
+    s.mbir(yd, 50, 20)
+    r_loop, p_loop = state(s)
+    assert s.frame_count() == 1
+    s.set_state(z, z, 0)
+    worst = (0.0, 0.0)
+    for it in range(50):
+        r_in, p_in = state(s)
+        if it % 20 == 0:
+            s.mbir(yd, 1, 1)
+            r_o, p_o = O.dh_mbir(yc, a, prm, iters=1, reset_every=1, r0=r_in, phi0=p_in)
+        else:
+            s.em(yd)
+            r_o, p_o = O.em(r_in, p_in, yc, a, prm)
+        r_g, p_g = state(s)
+        er, ep = M.rel_l2(r_g, r_o), M.phase_rms_diff(p_g, p_o, a)
+        worst = (max(worst[0], er), max(worst[1], ep))
+        assert er < TOL_R and ep < TOL_PHI, (it, er, ep)
+        assert np.all(p_g[a == 0] == 0.0)
+    say(f"  teacher-forced worst e_r={worst[0]:.2e} e_phi={worst[1]:.2e}")
+    np.testing.assert_array_equal(r_g, r_loop)
+    np.testing.assert_array_equal(p_g, p_loop)
+    r_o, p_o = O.dh_mbir(yc, a, prm, iters=50, reset_every=20)
+    S_g = M.strehl(p_loop, st.phase(0), a)
+    S_o = M.strehl(p_o, st.phase(0), a)
+    say(f"  Strehl after 50 iterations: GPU {S_g:.4f} oracle {S_o:.4f}")
+    assert abs(S_g - S_o) < TOL_S
+
+
+def test_full_bootstrap_reset_makes_the_run_independent_of_r0():
+    torch = _torch()
+    D = _ddh()
+    N = 64
+    st = synth.config0_stream()
+    _, gp = make_pair(N, st.sigma_w2, lam=1.0)
+    y = dev(st.frame(0))
+    rng = np.random.default_rng(4)
+    phi0 = dev(O.remove_tiptilt(0.2 * rng.standard_normal((N, N)), O.aperture(N)), np.float32)
+    outs = []
+    for r0 in (np.zeros((N, N)), rng.uniform(0.1, 2.0, (N, N))):
+        s = D.Stream(N, gp)
+        s.set_state(dev(r0, np.float32), phi0, 0)
+        s.mbir(y, 7, 3)
+        outs.append(state(s))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    with pytest.raises(D.DDHError):
+        s.mbir(y, -1, 3)
+    with pytest.raises(D.DDHError):
+        s.mbir(y, 5, 0)
+
+
 def test_zero_phase_prior_weight():
     D = _ddh()
     N = 64
