@@ -395,13 +395,27 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
   const float2* yv = use_args ? glb(a.y[xb.strm]) : glb(D.y);
   const int cur = use_args ? a.cur[xb.strm] : D.cur;
   const float* phi = glb(D.phi[cur]);
+  // descriptor fields are read once, here: read inside the loops they would
+  // be re-read after every store (which may alias the descriptor) and each
+  // re-read waits for every memory operation in flight
+  const float d2 = D.pupil_d2;
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + threadIdx.x];
+  // phi is loaded at every pixel (branch-free: a load under a per-pixel
+  // branch makes the compiler wait for all loads in flight at each join) and
+  // masked to the pupil afterwards
+  if (with_phi) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int idx = base + k * 256 + threadIdx.x;
-    ph[k] = (with_phi && in_pupil(idx / N, idx % N, N, D.pupil_d2)) ? phi[idx] : 0.0f;
+    for (int k = 0; k < 16; ++k) ph[k] = phi[base + k * 256 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int idx = base + k * 256 + threadIdx.x;
+      ph[k] = in_pupil(idx / N, idx % N, N, d2) ? ph[k] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ph[k] = 0.0f;
   }
   float s[2] = {0.f, 0.f};
 #pragma unroll
@@ -532,6 +546,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   const int row = xb.item * LPW + line;
   const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
   const float2* y = glb(D.y) + row * N;
+  const float d2 = D.pupil_d2;  // read before any store (see k_stats)
   // global reads first (they depend on nothing computed here): the row of y
   // and phi, and the twiddle table into LDS
   float2 yv[E];
@@ -564,7 +579,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
-    if (in_pupil(row, n, N, D.pupil_d2)) {
+    if (in_pupil(row, n, N, d2)) {
       const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, n, N) : phv[i];
       float sn, cs;
       fsincos(p, &sn, &cs);
@@ -602,6 +617,10 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
   float rpv[E];
   const float* rin = glb(D.r[(D.cur + k) & 1]);
   float* rmat = glb(D.r[((D.cur + k) & 1) ^ 1]);
+  // output pointers and constants are read before any store (see k_stats)
+  float* bbo = glb(D.bb);
+  float2* uo = glb(D.U);
+  const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor;
   // global reads first: the column, this thread's r values, the twiddles
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = glb(D.T)[first_pos<N, +1>(i, t) * N + col];
@@ -612,7 +631,6 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
   ColLds<W> L{lds + w};
   line_fft<N, +1>(v, t, L, s_tw);
   const float invN = 1.0f / (float)N;
-  const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = last_pos<N, +1>(i, t);
@@ -621,14 +639,14 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
     const float rp = rpv[i];
     const float ri = do_rinit ? rinit_of(rp, bb, lam, alpha, fl) : rp;
     const float wgt = wiener_of(ri, s2);
-    glb(D.bb)[n * N + col] = bb;
+    bbo[n * N + col] = bb;
     if (mat) rmat[n * N + col] = ri;  // the colour passes update this copy in place
     v[i] = cscale(b, wgt);
   }
   __syncthreads();
   line_fft<N, -1>(v, t, L, s_tw);
 #pragma unroll
-  for (int i = 0; i < E; ++i) glb(D.U)[last_pos<N, -1>(i, t) * N + col] = v[i];
+  for (int i = 0; i < E; ++i) uo[last_pos<N, -1>(i, t) * N + col] = v[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -680,6 +698,11 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   const float2* u = glb(D.U) + row * N;
   const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
   const float2* y = glb(D.y) + row * N;
+  // descriptor fields are read before any store (see k_stats)
+  const float d2 = D.pupil_d2;
+  const float c2s = 2.0f / D.sigma2;
+  float2* out = glb(D.T) + row * N;
+  float* pmat = glb(D.phi[((D.cur + k) & 1) ^ 1]) + row * N;
   // every global read is issued up front: the row, and y and phi at this
   // thread's output positions that lie in the pupil
   float2 yv[E];
@@ -691,7 +714,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
     const int m = last_pos<N, -1>(i, t);
     yv[i] = make_float2(0.f, 0.f);
     phv[i] = 0.f;
-    if (in_pupil(row, m, N, D.pupil_d2)) {
+    if (in_pupil(row, m, N, d2)) {
       yv[i] = y[m];
       phv[i] = phi[m];
     }
@@ -703,14 +726,11 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   const float2 mu = make_float2(sc[SC_MU_RE], sc[SC_MU_IM]);
   const float scale = sc[SC_SCALE];
   const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
-  const float c2s = 2.0f / D.sigma2;
-  float2* out = glb(D.T) + row * N;
-  float* pmat = glb(D.phi[((D.cur + k) & 1) ^ 1]) + row * N;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int m = last_pos<N, -1>(i, t);
     float2 res = make_float2(0.f, 0.f);
-    if (in_pupil(row, m, N, D.pupil_d2)) {
+    if (in_pupil(row, m, N, d2)) {
       const float2 z = cscale(v[i], invN);
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
       const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, m, N) : phv[i];
@@ -970,7 +990,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const float4* rin4 = reinterpret_cast<const float4*>(rin);
   const float4* pin4 = reinterpret_cast<const float4*>(pin);
   const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
-  const float2* ktp = glb(D.T);
+  const auto ktp = glb(D.T);
   float4 gr[SR], gb[SR], gph[SR];
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
