@@ -92,3 +92,31 @@ def test_stream_bytes_without_a_device():
     assert D.lib().ddh_stream_bytes(100, ctypes.byref(b)) == D.DDH_EINVAL
     assert D.lib().ddh_stream_bytes(64, None) == D.DDH_EINVAL
     assert D.stream_bytes(256) == sizes[2]
+
+
+def test_mbir_and_gradient_calls_validate_before_device_work():
+    L = ddh.lib()
+    one = ctypes.c_void_p(16)
+    assert L.ddh_mbir(None, one, 10, 5, None) == ddh.DDH_EINVAL
+    p64 = ddh.make_params(64)
+    out = ddh.GradOut()
+    ys = (ctypes.c_void_p * 3)(16, 16, 16)
+    # single stream: null parameters, K = 0, ckpt = 0, n_k != 1
+    assert L.ddh_unrolled_grad(None, 3, ys, one, one, 2, one, ctypes.byref(out), None) == ddh.DDH_EINVAL
+    assert L.ddh_unrolled_grad(ctypes.byref(p64), 0, ys, one, one, 2, one, ctypes.byref(out), None) == ddh.DDH_EINVAL
+    assert L.ddh_unrolled_grad(ctypes.byref(p64), 3, ys, one, one, 0, one, ctypes.byref(out), None) == ddh.DDH_EINVAL
+    p2 = ddh.make_params(64, n_k=2)
+    assert L.ddh_unrolled_grad(ctypes.byref(p2), 3, ys, one, one, 2, one, ctypes.byref(out), None) == ddh.DDH_EINVAL
+    nul = (ctypes.c_void_p * 3)(16, None, 16)
+    assert L.ddh_unrolled_grad(ctypes.byref(p64), 3, nul, one, one, 2, one, ctypes.byref(out), None) == ddh.DDH_EINVAL
+    # batch: no streams, mixed N, a null per-stream pointer
+    prm = (ddh.Params * 2)(ddh.make_params(64), ddh.make_params(128))
+    ptr2 = (ctypes.c_void_p * 2)(16, 16)
+    ys2 = (ctypes.c_void_p * 6)(16, 16, 16, 16, 16, 16)
+    outs = (ddh.GradOut * 2)()
+    B = L.ddh_unrolled_grad_batch
+    assert B(prm, 0, 3, ys2, ptr2, ptr2, 2, ptr2, outs, None) == ddh.DDH_EINVAL
+    assert B(prm, 2, 3, ys2, ptr2, ptr2, 2, ptr2, outs, None) == ddh.DDH_EINVAL
+    same = (ddh.Params * 2)(ddh.make_params(64), ddh.make_params(64))
+    half = (ctypes.c_void_p * 2)(16, None)
+    assert B(same, 2, 3, ys2, ptr2, half, 2, ptr2, outs, None) == ddh.DDH_EINVAL
