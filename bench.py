@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     p.add_argument("--graph", action="store_true", help="replay the batched step as a HIP graph (eager launches "
                    "are the default: they measured faster)")
+    p.add_argument("--lanes", type=int, default=1, help="split the batch into this many HIP streams (1-8)")
     p.add_argument("--serve", action="store_true", help="instead: the continuous-batching request loop (32 streams "
                    "at N in {128,256}, Poisson arrivals) against the one-frame-at-a-time loop")
     p.add_argument("--serve-rate", type=float, default=2000.0, help="aggregate frame arrival rate (Hz)")
@@ -499,7 +500,7 @@ def main():
     dev_frames = [[torch.from_numpy(frames[i][k]).cuda() for i in range(S)] for k in range(args.frames)]
     ptrs = [[t.data_ptr() for t in dev_frames[k]] for k in range(args.frames)]
     streams = [D.Stream(sp.N, gpu_params(D, sp.N, sims[i].sigma_w2)) for i, sp in enumerate(specs)]
-    batch = D.Batch(streams, graph=args.graph)
+    batch = D.Batch(streams, graph=args.graph, lanes=args.lanes)
     torch.cuda.synchronize()
 
     step = 0
@@ -532,7 +533,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "streams": S, "N": args.N if args.workload == "uniform" else "mixed",
                    "n_k": 1, "pixels_per_step": px_total, "frames_cycled": args.frames,
-                   "launch": "graph" if args.graph else "eager",
+                   "launch": "graph" if args.graph else "eager", "lanes": args.lanes,
                    "tiles": {str(k): v for k, v in tiles.items()}},
     }
 
