@@ -1694,6 +1694,14 @@ __device__ __forceinline__ bool g_pix(int& i, int& j, int N) {
   j = p - i * N;
   return p < N * N;
 }
+// one thread per 2 x 2 quad (one pixel of each colour): quad (qi, qj) holds
+// pixels (2qi + a, 2qj + b); its colour-C pixel is a = C & 1, b = C >> 1
+__device__ __forceinline__ bool g_quad(int& qi, int& qj, int N) {
+  const int q = blockIdx.x * 256 + threadIdx.x, h = N >> 1;
+  qi = q / h;
+  qj = q - qi * h;
+  return q < h * h;
+}
 // index of pixel (i, j) of this block's stream in a batched array
 __device__ __forceinline__ int g_at(int i, int j, int N) { return ((int)blockIdx.y * N + i) * N + j; }
 __device__ __forceinline__ void g_block_sums(double (&x)[3], double* part) {
@@ -1883,17 +1891,19 @@ __global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* p
   kap[p] = ka;
   tth[p] = tt;
 }
-// colour pass C of the r M-step, out of place (rin -> rout)
+// colour pass C of the r M-step, out of place (rin -> rout): one thread per
+// quad updates its colour-C pixel and copies the other three
 template <int C>
 __global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* s, const GradPrm* Pd, float* rout) {
   const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  if ((i & 1) + 2 * (j & 1) != C) {
-    rout[p] = rin[p];
-    return;
-  }
+  int qi, qj;
+  if (!g_quad(qi, qj, P.N)) return;
+  const int N = P.N;
+  const int p00 = g_at(2 * qi, 2 * qj, N);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q != C) rout[p00 + (q & 1) * N + (q >> 1)] = rin[p00 + (q & 1) * N + (q >> 1)];
+  const int i = 2 * qi + (C & 1), j = 2 * qj + (C >> 1), p = p00 + (C & 1) * N + (C >> 1);
   const bool up = i > 0, dn = i < N - 1, lf = j > 0, rt = j < N - 1;
   float rq[8];
   rq[0] = up ? rin[p - N] : 0.f;
@@ -1906,15 +1916,20 @@ __global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* 
   rq[7] = (dn && rt) ? rin[p + N + 1] : 0.f;
   rout[p] = r_pixel<true>(rin[p], s[p], rq, nb_mask(i, j, N), P.inv_sp, P.lc, P.pmq, P.qop, P.fl);
 }
-// colour pass C of the phi M-step, out of place
+// colour pass C of the phi M-step, out of place, one thread per quad
 template <int C>
 __global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* kap, const float* tth,
                                                  const GradPrm* Pd, float* pout) {
   const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) {
+  int qi, qj;
+  if (!g_quad(qi, qj, P.N)) return;
+  const int N = P.N;
+  const int p00 = g_at(2 * qi, 2 * qj, N);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q != C) pout[p00 + (q & 1) * N + (q >> 1)] = pin[p00 + (q & 1) * N + (q >> 1)];
+  const int i = 2 * qi + (C & 1), j = 2 * qj + (C >> 1), p = p00 + (C & 1) * N + (C >> 1);
+  if (!in_pupil(i, j, N, P.d2)) {
     pout[p] = pin[p];
     return;
   }
@@ -1943,34 +1958,46 @@ __global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const floa
   pbar[p] = in_pupil(i, j, P.N, P.d2) ? (phi[p] - ptrue[p] - dmean) * inv_nL : 0.f;
 }
 // phi pass C reversed, part a: the colour-C pupil pixels hand their adjoint to
-// kappa, theta~, beta and (as em = pbar 2 beta / den) to their neighbours
+// kappa, theta~, beta and (as em = pbar 2 beta / den) to their neighbours.
+// One thread per quad; kbar and tbar are assigned (every pixel is of exactly
+// one colour, so the four passes write each once).
 template <int C>
 __global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float* pout, const float* kap,
                                                    const float* tth, const GradPrm* Pd, float* pbar, float* em,
                                                    float* kbar, float* tbar, float* gbeta) {
   const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  em[p] = 0.f;
-  if ((i & 1) + 2 * (j & 1) != C || !in_pupil(i, j, N, P.d2)) return;
-  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
-  float Ph = 0.f;
+  int qi, qj;
+  if (!g_quad(qi, qj, P.N)) return;
+  const int N = P.N;
+  const int p00 = g_at(2 * qi, 2 * qj, N);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int ii = i + nb[e][0], jj = j + nb[e][1];
-    if (ii >= 0 && ii < N && jj >= 0 && jj < N) Ph += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * pin[g_at(ii, jj, N)];
+  for (int q = 0; q < 4; ++q)
+    if (q != C) em[p00 + (q & 1) * N + (q >> 1)] = 0.f;
+  const int i = 2 * qi + (C & 1), j = 2 * qj + (C >> 1), p = p00 + (C & 1) * N + (C >> 1);
+  float emv = 0.f, kb = 0.f, tb = 0.f;
+  if (in_pupil(i, j, N, P.d2)) {
+    const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+    float Ph = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ii = i + nb[e][0], jj = j + nb[e][1];
+      if (ii >= 0 && ii < N && jj >= 0 && jj < N) Ph += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * pin[g_at(ii, jj, N)];
+    }
+    const float Pw = pupil_weight_of(pupil_nbr_12(i, j, N, P.d2));
+    const float ka = kap[p], beta2 = 2.0f * P.beta;
+    const float den = ka + beta2 * Pw;
+    if (den > 0.0f) {  // otherwise the pixel kept its value: its adjoint passes through
+      const float g = pbar[p], inv = 1.0f / den, out = pout[p];
+      emv = g * beta2 * inv;
+      kb = g * (tth[p] - out) * inv;
+      tb = g * ka * inv;
+      gbeta[p] += g * 2.0f * (Ph - Pw * out) * inv;
+      pbar[p] = 0.f;
+    }
   }
-  const float Pw = pupil_weight_of(pupil_nbr_12(i, j, N, P.d2));
-  const float ka = kap[p], beta2 = 2.0f * P.beta;
-  const float den = ka + beta2 * Pw;
-  if (!(den > 0.0f)) return;  // the pixel kept its value: its adjoint passes through
-  const float g = pbar[p], inv = 1.0f / den, out = pout[p];
-  em[p] = g * beta2 * inv;
-  kbar[p] += g * (tth[p] - out) * inv;
-  tbar[p] += g * ka * inv;
-  gbeta[p] += g * 2.0f * (Ph - Pw * out) * inv;
-  pbar[p] = 0.f;
+  em[p] = emv;
+  kbar[p] = kb;
+  tbar[p] = tb;
 }
 // part b: pupil pixels gather em of their colour-C pupil neighbours
 __global__ __launch_bounds__(256) void k_g_pback_b(const float* em, const GradPrm* Pd, float* pbar) {
@@ -1988,15 +2015,17 @@ __global__ __launch_bounds__(256) void k_g_pback_b(const float* em, const GradPr
   }
   pbar[p] += acc;
 }
-// data term reversed: (kbar, tbar) -> phi' (pb2 += ...), z (zbar), s2
+// data term reversed: (kbar, tbar) -> phi' (pb2 = pbar + ...), z (zbar), s2
 __global__ __launch_bounds__(256) void k_g_data_bar(const float2* yh, const float* phip, const float2* z,
                                                     const float* kap, const float* kbar, const float* tbar,
-                                                    const GradPrm* Pd, float* pb2, float2* zbar, float* gs2) {
+                                                    const float* pbar, const GradPrm* Pd, float* pb2, float2* zbar,
+                                                    float* gs2) {
   const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
   const int p = g_at(i, j, P.N);
   zbar[p] = make_float2(0.f, 0.f);
+  pb2[p] = pbar[p];  // pb2 starts as the phase adjoint left by the passes
   if (!in_pupil(i, j, P.N, P.d2)) return;
   float ur, ui;
   g_data_u(yh[p], phip[p], z[p], ur, ui);
@@ -2041,18 +2070,18 @@ __device__ __forceinline__ void g_shape(float d, const GradPrm& P, float& sh, fl
   dsh_dsig = P.pmq > 0.0f ? dsh_dv * (-P.pmq * v / P.sig_r) : 0.0f;
 }
 // r pass C reversed, part a: colour-C pixels turn their adjoint into (Abar,
-// Bbar, sbar), their own old value's adjoint and the sigma_r gradient
+// Bbar, sbar), their own old value's adjoint and the sigma_r gradient.  One
+// thread per quad; Abar and Bbar are written at colour-C pixels only (part b
+// reads nothing else) and sbar is assigned (each pixel once over the passes).
 template <int C>
 __global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float* rout, const float* s,
                                                    const GradPrm* Pd, float* rbar, float* sbar, float* Abar,
                                                    float* Bbar, float* gsr) {
   const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  Abar[p] = 0.f;
-  Bbar[p] = 0.f;
-  if ((i & 1) + 2 * (j & 1) != C) return;
+  int qi, qj;
+  if (!g_quad(qi, qj, P.N)) return;
+  const int N = P.N;
+  const int i = 2 * qi + (C & 1), j = 2 * qj + (C >> 1), p = g_at(i, j, N);
   const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
   const float ri = rin[p];
   float A = 0.f, B = 0.f;
@@ -2069,31 +2098,35 @@ __global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float
     B += W[e] * sh[e] * rq[e];
   }
   const float g = rbar[p];
-  rbar[p] = 0.f;
   const float rho = rout[p];
-  if (!(rho > P.fl)) return;  // floored: no dependence on the inputs
-  if (!(A > 0.0f)) {          // no prior: rho = s
-    sbar[p] += g;
-    return;
+  float ab = 0.f, bb = 0.f, sb = 0.f, own = 0.f;
+  if (rho > P.fl) {         // floored: no dependence on the inputs
+    if (!(A > 0.0f)) {      // no prior: rho = s
+      sb = g;
+    } else {
+      const float fp = (3.0f * A * rho - 2.0f * B) * rho + 1.0f;
+      if (fp != 0.0f) {
+        const float inv = 1.0f / fp;
+        ab = -g * rho * rho * rho * inv;
+        bb = g * rho * rho * inv;
+        sb = g * inv;
+        float gs = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (!ok[e]) continue;
+          const float shb = W[e] * (ab + bb * rq[e]);  // adjoint of sh_e
+          own += shb * dsh[e];
+          // d(W sh)/d sigma_r = -2 W sh / sigma_r + W dsh/dsigma
+          gs += (ab + bb * rq[e]) * (-2.0f * W[e] * sh[e] / P.sig_r + W[e] * dss[e]);
+        }
+        gsr[p] += gs;
+      }
+    }
   }
-  const float fp = (3.0f * A * rho - 2.0f * B) * rho + 1.0f;
-  if (fp == 0.0f) return;
-  const float inv = 1.0f / fp;
-  const float ab = -g * rho * rho * rho * inv, bb = g * rho * rho * inv;
-  sbar[p] += g * inv;
   Abar[p] = ab;
   Bbar[p] = bb;
-  float own = 0.f, gs = 0.f;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    if (!ok[e]) continue;
-    const float shb = W[e] * (ab + bb * rq[e]);  // adjoint of sh_e
-    own += shb * dsh[e];
-    // d(W sh)/d sigma_r = -2 W sh / sigma_r + W dsh/dsigma
-    gs += (ab + bb * rq[e]) * (-2.0f * W[e] * sh[e] / P.sig_r + W[e] * dss[e]);
-  }
+  sbar[p] = sb;
   rbar[p] = own;
-  gsr[p] += gs;
 }
 // part b: every pixel not of colour C gathers from its colour-C neighbours
 template <int C>
@@ -2174,6 +2207,7 @@ __global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, const Gra
 }
 
 #define DDH_G_GRID(N, B) dim3(((N) * (N) + 255) / 256, (B)), dim3(256), 0, st
+#define DDH_G_QGRID(N, B) dim3(((N) * (N) / 4 + 255) / 256, (B)), dim3(256), 0, st
 static int g_nb(int N) { return (N * N + 255) / 256; }
 
 hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st) {
@@ -2192,14 +2226,14 @@ hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hi
   e = launch_fft2(N, B, a.mu, a.z, a.work, a.tw, 0, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N, B), a.yh, a.phip, a.z, d.prm, a.kap, a.tth);
-  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_GRID(N, B), a.rs[0], a.s, d.prm, a.rs[1]);
-  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_GRID(N, B), a.rs[1], a.s, d.prm, a.rs[2]);
-  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_GRID(N, B), a.rs[2], a.s, d.prm, a.rs[3]);
-  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_GRID(N, B), a.rs[3], a.s, d.prm, a.rs[4]);
-  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_GRID(N, B), a.phip, a.kap, a.tth, d.prm, a.ps[1]);
-  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_GRID(N, B), a.ps[1], a.kap, a.tth, d.prm, a.ps[2]);
-  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_GRID(N, B), a.ps[2], a.kap, a.tth, d.prm, a.ps[3]);
-  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_GRID(N, B), a.ps[3], a.kap, a.tth, d.prm, a.ps[4]);
+  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_QGRID(N, B), a.rs[0], a.s, d.prm, a.rs[1]);
+  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_QGRID(N, B), a.rs[1], a.s, d.prm, a.rs[2]);
+  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_QGRID(N, B), a.rs[2], a.s, d.prm, a.rs[3]);
+  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_QGRID(N, B), a.rs[3], a.s, d.prm, a.rs[4]);
+  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_QGRID(N, B), a.phip, a.kap, a.tth, d.prm, a.ps[1]);
+  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_QGRID(N, B), a.ps[1], a.kap, a.tth, d.prm, a.ps[2]);
+  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_QGRID(N, B), a.ps[2], a.kap, a.tth, d.prm, a.ps[3]);
+  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_QGRID(N, B), a.ps[3], a.kap, a.tth, d.prm, a.ps[4]);
   return hipGetLastError();
 }
 hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d, int N, int B, float* pbar,
@@ -2213,32 +2247,27 @@ hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d,
 // frame reversed: pbar (adjoint of the frame's output phase) becomes the
 // adjoint of its input phase, rbar likewise for r; gs2, gsr, gbeta accumulate
 hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st) {
-  const long long n = (long long)B * N * N;
-  hipError_t e = launch_fill_zero(g.kbar, n, st);
-  if (e == hipSuccess) e = launch_fill_zero(g.tbar, n, st);
-  if (e == hipSuccess) e = launch_fill_zero(g.sbar, n, st);
-  if (e != hipSuccess) return e;
+  // kbar, tbar (phi passes) and sbar (r passes) are assigned at every pixel
+  // by the four passes, so they need no clearing
   // phi sweep reversed (ps[c] = input of pass c, ps[0] = phi')
   const float* ps0 = a.phip;
-#define DDH_PB(C)                                                                                        \
-  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_GRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, \
-                     d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta);                                       \
+#define DDH_PB(C)                                                                                         \
+  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_QGRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, \
+                     d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta);                                        \
   hipLaunchKernelGGL(k_g_pback_b, DDH_G_GRID(N, B), g.em, d.prm, g.pbar);
   DDH_PB(3) DDH_PB(2) DDH_PB(1) DDH_PB(0)
 #undef DDH_PB
-  e = launch_copy(g.pb2, g.pbar, n, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, d.prm, g.pb2, g.zbar,
-                     g.gs2);
+  hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, g.pbar, d.prm, g.pb2,
+                     g.zbar, g.gs2);
   // r sweep reversed (rs[c] = input of pass c)
-#define DDH_RB(C)                                                                                               \
-  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_GRID(N, B), a.rs[C], a.rs[C + 1], a.s, d.prm, g.rbar, g.sbar, g.Abar, \
-                     g.Bbar, g.gsr);                                                                           \
+#define DDH_RB(C)                                                                                                \
+  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_QGRID(N, B), a.rs[C], a.rs[C + 1], a.s, d.prm, g.rbar, g.sbar, g.Abar, \
+                     g.Bbar, g.gsr);                                                                            \
   hipLaunchKernelGGL(k_g_rback_b<C>, DDH_G_GRID(N, B), a.rs[C], g.Abar, g.Bbar, d.prm, g.rbar);
   DDH_RB(3) DDH_RB(2) DDH_RB(1) DDH_RB(0)
 #undef DDH_RB
   // z = F mu  ->  mubar = F^H zbar
-  e = launch_fft2(N, B, g.zbar, g.mubar, a.work, a.tw, 1, st);
+  hipError_t e = launch_fft2(N, B, g.zbar, g.mubar, a.work, a.tw, 1, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_estep_bar, DDH_G_GRID(N, B), a.r_in, a.b, a.rs[0], g.mubar, g.sbar, d.prm, g.rbar, g.bbar,
                      g.gs2);
@@ -2260,5 +2289,6 @@ hipError_t g_launch_totals(const GradBwd& g, const GradDev& d, int N, int B, hip
   return hipGetLastError();
 }
 #undef DDH_G_GRID
+#undef DDH_G_QGRID
 
 }  // namespace ddh
