@@ -113,10 +113,6 @@ hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st
 hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st);
 
 // --- unrolled frames with a hand-written adjoint (ddh_kernels.hip) ---------
-// frame scalars: normalisation and the tip/tilt plane (FP64 sums combined on the device)
-struct GradScal {
-  float mu_re, mu_im, scale, c0, c1, c2;
-};
 // one stream's constants (a device array of these, one per stream of a batch)
 struct GradPrm {
   int N;
@@ -130,12 +126,9 @@ struct GradLoss {
 struct GradDev {
   const GradPrm* prm;  // [B]
   const double* minv;  // [B][6] inverse pupil moment matrix (symmetric, upper triangle)
-  GradScal* scal;      // [B] Normalize and plane of the frame being run
-  GradScal* bscal;     // [B] plane of the phase adjoint
   GradLoss* loss;      // [B]
-  double* tot;         // [B][3] sums of gs2, gsr, gbeta
   int* flag;           // [B] bit 1: a frame could not be normalised; bit 2: zero loss
-  double* part;        // [B][nb][3] FP64 block partials
+  double* part;        // [B][g_records(N)][6] FP64 reduction records
 };
 // one frame's inputs, intermediates and outputs; arrays are B images of N*N
 // back to back
@@ -160,5 +153,6 @@ hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d,
                          hipStream_t st);
 hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st);
 hipError_t g_launch_totals(const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st);
+int g_records(int N);  // reduction records per stream
 
 }  // namespace ddh

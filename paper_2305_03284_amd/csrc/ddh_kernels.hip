@@ -1704,145 +1704,173 @@ __device__ __forceinline__ bool g_quad(int& qi, int& qj, int N) {
 }
 // index of pixel (i, j) of this block's stream in a batched array
 __device__ __forceinline__ int g_at(int i, int j, int N) { return ((int)blockIdx.y * N + i) * N + j; }
-__device__ __forceinline__ void g_block_sums(double (&x)[3], double* part) {
-  __shared__ double red[3][4];
+// Reductions (Normalize, the tip/tilt planes, the loss, the scalar
+// gradients): 16 pixels per thread and G_RED_PIX per block, each block
+// writing one record of NV FP64 sums; the kernel that needs the result sums
+// its stream's records (at most 64, N <= 512) in its first wavefront.
+constexpr int G_RED_PIX = 4096;
+__host__ __device__ constexpr int g_nred(int N) { return (N * N) / G_RED_PIX; }
+template <int NV>
+__device__ __forceinline__ void g_block_record(double (&x)[NV], double* part) {
+  __shared__ double red[NV][4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) x[k] = wave_sum_d(x[k]);
+  for (int k = 0; k < NV; ++k) x[k] = wave_sum_d(x[k]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) red[k][wv] = x[k];
+    for (int k = 0; k < NV; ++k) red[k][wv] = x[k];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      part[(blockIdx.y * gridDim.x + blockIdx.x) * 3 + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+    for (int k = 0; k < NV; ++k)
+      part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
 }
-
-// sums of Re y, Im y, |y|^2 (FP64 block partials)
-__global__ __launch_bounds__(256) void k_g_ysum(const float2* const* ys, int N, double* part) {
-  int i, j;
-  double x[3] = {0, 0, 0};
-  if (g_pix(i, j, N)) {
-    const float2 v = ys[blockIdx.y][i * N + j];
-    x[0] = v.x;
-    x[1] = v.y;
-    x[2] = (double)v.x * v.x + (double)v.y * v.y;
+// the stream's totals, in every lane of the calling wavefront
+template <int NV>
+__device__ __forceinline__ void g_wave_totals(const double* part, int nred, double (&t)[NV]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double v = lane < nred ? part[((size_t)blockIdx.y * nred + lane) * NV + k] : 0.0;
+    t[k] = wave_sum_d(v);
   }
-  g_block_sums(x, part);
 }
-// plane-fit sums over the pupil of f: sum f, sum (i-c) f, sum (j-c) f
+__device__ __forceinline__ int g_red_pix(int e) { return blockIdx.x * G_RED_PIX + e * 256 + threadIdx.x; }
+
+// frame statistics: sums of Re y, Im y, |y|^2 and the plane-fit sums over the
+// pupil of the incoming phase: sum phi, sum (i-c) phi, sum (j-c) phi
+__global__ __launch_bounds__(256) void k_g_stats(const float2* const* ys, const float* phi, const GradPrm* Pd,
+                                                 double* part) {
+  const int N = Pd[blockIdx.y].N;
+  const float d2 = Pd[blockIdx.y].d2;
+  const float2* y = ys[blockIdx.y];
+  const float* ph = phi + (size_t)blockIdx.y * N * N;
+  float2 v[16];
+  float f[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    v[e] = y[g_red_pix(e)];
+    f[e] = ph[g_red_pix(e)];
+  }
+  const double c = 0.5 * (N - 1);
+  double x[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int pix = g_red_pix(e), i = pix / N, j = pix - i * N;
+    x[0] += v[e].x;
+    x[1] += v[e].y;
+    x[2] += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
+    if (in_pupil(i, j, N, d2)) {
+      x[3] += f[e];
+      x[4] += (i - c) * f[e];
+      x[5] += (j - c) * f[e];
+    }
+  }
+  g_block_record<6>(x, part);
+}
+// plane-fit sums over the pupil of f (the phase adjoint before the tip/tilt
+// projection)
 __global__ __launch_bounds__(256) void k_g_psum(const float* f, const GradPrm* Pd, double* part) {
   const int N = Pd[blockIdx.y].N;
   const float d2 = Pd[blockIdx.y].d2;
-  int i, j;
+  const float* fs = f + (size_t)blockIdx.y * N * N;
+  float v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = fs[g_red_pix(e)];
+  const double c = 0.5 * (N - 1);
   double x[3] = {0, 0, 0};
-  if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
-    const double c = 0.5 * (N - 1), v = f[g_at(i, j, N)];
-    x[0] = v;
-    x[1] = (i - c) * v;
-    x[2] = (j - c) * v;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int pix = g_red_pix(e), i = pix / N, j = pix - i * N;
+    if (in_pupil(i, j, N, d2)) {
+      x[0] += v[e];
+      x[1] += (i - c) * v[e];
+      x[2] += (j - c) * v[e];
+    }
   }
-  g_block_sums(x, part);
+  g_block_record<3>(x, part);
 }
-// piston-removed phase error sums over the pupil: sum d, sum d^2, d = phi - phi_true
+// piston-removed phase error sums over the pupil: sum d, sum d^2, count, d = phi - phi_true
 __global__ __launch_bounds__(256) void k_g_dsum(const float* phi, const float* ptrue, const GradPrm* Pd,
                                                 double* part) {
   const int N = Pd[blockIdx.y].N;
   const float d2 = Pd[blockIdx.y].d2;
-  int i, j;
-  double x[3] = {0, 0, 0};
-  if (g_pix(i, j, N) && in_pupil(i, j, N, d2)) {
-    const int p = g_at(i, j, N);
-    const double d = (double)phi[p] - ptrue[p];
-    x[0] = d;
-    x[1] = d * d;
-    x[2] = 1.0;
+  const size_t o = (size_t)blockIdx.y * N * N;
+  float a[16], t[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    a[e] = phi[o + g_red_pix(e)];
+    t[e] = ptrue[o + g_red_pix(e)];
   }
-  g_block_sums(x, part);
+  double x[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int pix = g_red_pix(e), i = pix / N, j = pix - i * N;
+    if (in_pupil(i, j, N, d2)) {
+      const double d = (double)a[e] - t[e];
+      x[0] += d;
+      x[1] += d * d;
+      x[2] += 1.0;
+    }
+  }
+  g_block_record<3>(x, part);
 }
-
 // sums over the whole image of the three per-pixel gradient accumulators
 __global__ __launch_bounds__(256) void k_g_tsum(const float* a0, const float* a1, const float* a2, int N,
                                                 double* part) {
-  int i, j;
+  const size_t o = (size_t)blockIdx.y * N * N;
   double x[3] = {0, 0, 0};
-  if (g_pix(i, j, N)) {
-    const int p = g_at(i, j, N);
-    x[0] = a0[p];
-    x[1] = a1[p];
-    x[2] = a2[p];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const size_t q = o + g_red_pix(e);
+    x[0] += a0[q];
+    x[1] += a1[q];
+    x[2] += a2[q];
   }
-  g_block_sums(x, part);
+  g_block_record<3>(x, part);
 }
-// One block per stream: the stream's nb block partials, summed in FP64, turned
-// into the scalars the next kernels read.
-//   G_NORM : Normalize (Eq. 4): mean and 1/std of y -> S (flag bit 1 if y is constant)
-//   G_PLANE: least-squares plane c = M^{-1} (sum f, sum (i-c) f, sum (j-c) f) -> S
-//   G_LOSS : piston-removed RMS phase error -> Lo (flag bit 2 if it is zero)
-//   G_TOTAL: the three sums -> tot
-enum { G_NORM = 0, G_PLANE = 1, G_LOSS = 2, G_TOTAL = 3 };
-template <int MODE>
-__global__ __launch_bounds__(256) void k_g_combine(const double* part, int nb, int N, const double* minv,
-                                                   GradScal* S, GradLoss* Lo, double* tot, int* flag) {
-  const int b = blockIdx.x;
-  double x[3] = {0, 0, 0};
-  for (int q = threadIdx.x; q < nb; q += 256)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) x[k] += part[((size_t)b * nb + q) * 3 + k];
-  __shared__ double red[3][4];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) x[k] = wave_sum_d(x[k]);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) red[k][wv] = x[k];
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double t[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
-  if constexpr (MODE == G_NORM) {
-    const double px = (double)N * N, mr = t[0] / px, mi = t[1] / px;
-    const double m2 = t[2] - px * (mr * mr + mi * mi);
-    const bool ok = m2 > 0.0 && m2 < HUGE_VAL;
-    S[b].mu_re = (float)mr;
-    S[b].mu_im = (float)mi;
-    S[b].scale = ok ? (float)sqrt(px / m2) : 0.0f;
-    if (!ok) flag[b] = flag[b] | 1;
-  } else if constexpr (MODE == G_PLANE) {
-    const double* M = minv + 6 * b;
-    S[b].c0 = (float)(M[0] * t[0] + M[1] * t[1] + M[2] * t[2]);
-    S[b].c1 = (float)(M[1] * t[0] + M[3] * t[1] + M[4] * t[2]);
-    S[b].c2 = (float)(M[2] * t[0] + M[4] * t[1] + M[5] * t[2]);
-  } else if constexpr (MODE == G_LOSS) {
-    const double n = t[2], dmean = t[0] / n, var = t[1] / n - dmean * dmean;
-    const double L = sqrt(var > 0.0 ? var : 0.0);
-    Lo[b].dmean = (float)dmean;
-    Lo[b].inv_nL = L > 0.0 ? (float)(1.0 / (n * L)) : 0.0f;
-    Lo[b].loss = L;
-    if (!(L > 0.0)) flag[b] = flag[b] | 2;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) tot[3 * b + k] = t[k];
-  }
+// the least-squares plane of a stream from its plane-fit totals
+__device__ __forceinline__ void g_plane(const double* minv, const double (&t)[3], float* c) {
+  const double* M = minv + 6 * blockIdx.y;
+  c[0] = (float)(M[0] * t[0] + M[1] * t[1] + M[2] * t[2]);
+  c[1] = (float)(M[1] * t[0] + M[3] * t[1] + M[4] * t[2]);
+  c[2] = (float)(M[2] * t[0] + M[4] * t[1] + M[5] * t[2]);
 }
 
-// frame prologue: yhat, phi' (plane removed, zero off the pupil), v = a exp(-j phi') yhat
+// frame prologue: Normalize (Eq. 4) and the plane from the stats records
+// (first wavefront; flag bit 1 if y is constant), then per pixel yhat, phi'
+// (plane removed, zero off the pupil), v = a exp(-j phi') yhat
 __global__ __launch_bounds__(256) void k_g_prologue(const float2* const* ys, const float* phi, const GradPrm* Pd,
-                                                    const GradScal* Sd, float2* yh, float* phip, float2* v) {
+                                                    const double* minv, const double* part, int* flag, float2* yh,
+                                                    float* phip, float2* v) {
   const GradPrm P = Pd[blockIdx.y];
-  const GradScal S = Sd[blockIdx.y];
+  __shared__ float sc[6];
+  if (threadIdx.x < 64) {
+    double t[6];
+    g_wave_totals<6>(part, g_nred(P.N), t);
+    if (threadIdx.x == 0) {
+      const double px = (double)P.N * P.N, mr = t[0] / px, mi = t[1] / px;
+      const double m2 = t[2] - px * (mr * mr + mi * mi);
+      const bool ok = m2 > 0.0 && m2 < HUGE_VAL;
+      sc[0] = (float)mr;
+      sc[1] = (float)mi;
+      sc[2] = ok ? (float)sqrt(px / m2) : 0.0f;
+      const double tp[3] = {t[3], t[4], t[5]};
+      g_plane(minv, tp, sc + 3);
+      if (!ok && blockIdx.x == 0) flag[blockIdx.y] = flag[blockIdx.y] | 1;
+    }
+  }
+  __syncthreads();
   int i, j;
   if (!g_pix(i, j, P.N)) return;
   const int p = g_at(i, j, P.N);
   const float2 yy = ys[blockIdx.y][i * P.N + j];
-  const float2 h = make_float2((yy.x - S.mu_re) * S.scale, (yy.y - S.mu_im) * S.scale);
+  const float2 h = make_float2((yy.x - sc[0]) * sc[2], (yy.y - sc[1]) * sc[2]);
   yh[p] = h;
   float ph = 0.f;
   float2 vv = make_float2(0.f, 0.f);
   if (in_pupil(i, j, P.N, P.d2)) {
-    ph = phi[p] - plane_val(S.c0, S.c1, S.c2, i, j, P.N);
+    ph = phi[p] - plane_val(sc[3], sc[4], sc[5], i, j, P.N);
     float sn, cs;
     fsincos(ph, &sn, &cs);
     vv = cmul(h, make_float2(cs, -sn));
@@ -1947,15 +1975,34 @@ __global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* 
 }
 
 // ---------------------------------------------------------------- adjoint
-// loss: L = sqrt(mean(d - mean d)^2) over the pupil; dL/dphi = (d - mean d)/(n L)
+// loss: L = sqrt(mean(d - mean d)^2) over the pupil; dL/dphi = (d - mean d)/(n L).
+// The first wavefront combines the dsum records; block 0 stores the loss
+// (flag bit 2 if it is zero)
 __global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const float* ptrue, const GradPrm* Pd,
-                                                    const GradLoss* Lo, float* pbar) {
+                                                    const double* part, GradLoss* Lo, int* flag, float* pbar) {
   const GradPrm P = Pd[blockIdx.y];
-  const float dmean = Lo[blockIdx.y].dmean, inv_nL = Lo[blockIdx.y].inv_nL;
+  __shared__ float sc[2];
+  if (threadIdx.x < 64) {
+    double t[3];
+    g_wave_totals<3>(part, g_nred(P.N), t);
+    if (threadIdx.x == 0) {
+      const double n = t[2], dmean = t[0] / n, var = t[1] / n - dmean * dmean;
+      const double L = sqrt(var > 0.0 ? var : 0.0);
+      sc[0] = (float)dmean;
+      sc[1] = L > 0.0 ? (float)(1.0 / (n * L)) : 0.0f;
+      if (blockIdx.x == 0) {
+        Lo[blockIdx.y].dmean = sc[0];
+        Lo[blockIdx.y].inv_nL = sc[1];
+        Lo[blockIdx.y].loss = L;
+        if (!(L > 0.0)) flag[blockIdx.y] = flag[blockIdx.y] | 2;
+      }
+    }
+  }
+  __syncthreads();
   int i, j;
   if (!g_pix(i, j, P.N)) return;
   const int p = g_at(i, j, P.N);
-  pbar[p] = in_pupil(i, j, P.N, P.d2) ? (phi[p] - ptrue[p] - dmean) * inv_nL : 0.f;
+  pbar[p] = in_pupil(i, j, P.N, P.d2) ? (phi[p] - ptrue[p] - sc[0]) * sc[1] : 0.f;
 }
 // phi pass C reversed, part a: the colour-C pupil pixels hand their adjoint to
 // kappa, theta~, beta and (as em = pbar 2 beta / den) to their neighbours.
@@ -2195,31 +2242,31 @@ __global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const floa
   const float2 v = cmul(yh[p], make_float2(cs, -sn)), vb = vbar[p];
   pb2[p] += vb.x * v.y - vb.y * v.x;
 }
-// tip/tilt removal reversed: pbar = pupil ? pb2 - plane(pb2) : 0
-__global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, const GradPrm* Pd, const GradScal* Sd,
-                                                     float* pbar) {
+// tip/tilt removal reversed: pbar = pupil ? pb2 - plane(pb2) : 0, the plane
+// from the psum records (first wavefront)
+__global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, const GradPrm* Pd, const double* minv,
+                                                     const double* part, float* pbar) {
   const GradPrm P = Pd[blockIdx.y];
-  const GradScal S = Sd[blockIdx.y];
+  __shared__ float sc[3];
+  if (threadIdx.x < 64) {
+    double t[3];
+    g_wave_totals<3>(part, g_nred(P.N), t);
+    if (threadIdx.x == 0) g_plane(minv, t, sc);
+  }
+  __syncthreads();
   int i, j;
   if (!g_pix(i, j, P.N)) return;
   const int p = g_at(i, j, P.N);
-  pbar[p] = in_pupil(i, j, P.N, P.d2) ? pb2[p] - plane_val(S.c0, S.c1, S.c2, i, j, P.N) : 0.f;
+  pbar[p] = in_pupil(i, j, P.N, P.d2) ? pb2[p] - plane_val(sc[0], sc[1], sc[2], i, j, P.N) : 0.f;
 }
 
 #define DDH_G_GRID(N, B) dim3(((N) * (N) + 255) / 256, (B)), dim3(256), 0, st
 #define DDH_G_QGRID(N, B) dim3(((N) * (N) / 4 + 255) / 256, (B)), dim3(256), 0, st
-static int g_nb(int N) { return (N * N + 255) / 256; }
+#define DDH_G_RGRID(N, B) dim3(g_nred(N), (B)), dim3(256), 0, st
 
 hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st) {
-  const int nb = g_nb(N);
-  // Normalize and the tip/tilt plane of the incoming phase
-  hipLaunchKernelGGL(k_g_ysum, DDH_G_GRID(N, B), a.y, N, d.part);
-  hipLaunchKernelGGL(k_g_combine<G_NORM>, dim3(B), dim3(256), 0, st, d.part, nb, N, d.minv, d.scal, d.loss, d.tot,
-                     d.flag);
-  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N, B), a.phi_in, d.prm, d.part);
-  hipLaunchKernelGGL(k_g_combine<G_PLANE>, dim3(B), dim3(256), 0, st, d.part, nb, N, d.minv, d.scal, d.loss, d.tot,
-                     d.flag);
-  hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N, B), a.y, a.phi_in, d.prm, d.scal, a.yh, a.phip, a.v);
+  hipLaunchKernelGGL(k_g_stats, DDH_G_RGRID(N, B), a.y, a.phi_in, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N, B), a.y, a.phi_in, d.prm, d.minv, d.part, d.flag, a.yh, a.phip, a.v);
   hipError_t e = launch_fft2(N, B, a.v, a.b, a.work, a.tw, 1, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_estep, DDH_G_GRID(N, B), a.r_in, a.b, d.prm, a.rs[0], a.mu, a.s);
@@ -2238,10 +2285,8 @@ hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hi
 }
 hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d, int N, int B, float* pbar,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_g_dsum, DDH_G_GRID(N, B), phi, ptrue, d.prm, d.part);
-  hipLaunchKernelGGL(k_g_combine<G_LOSS>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.scal, d.loss,
-                     d.tot, d.flag);
-  hipLaunchKernelGGL(k_g_loss_bar, DDH_G_GRID(N, B), phi, ptrue, d.prm, d.loss, pbar);
+  hipLaunchKernelGGL(k_g_dsum, DDH_G_RGRID(N, B), phi, ptrue, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_loss_bar, DDH_G_GRID(N, B), phi, ptrue, d.prm, d.part, d.loss, d.flag, pbar);
   return hipGetLastError();
 }
 // frame reversed: pbar (adjoint of the frame's output phase) becomes the
@@ -2276,19 +2321,18 @@ hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_bp_bar, DDH_G_GRID(N, B), g.vbar, a.yh, a.phip, d.prm, g.pb2);
   // tip/tilt removal reversed: the plane of pb2 over the pupil, subtracted
-  hipLaunchKernelGGL(k_g_psum, DDH_G_GRID(N, B), g.pb2, d.prm, d.part);
-  hipLaunchKernelGGL(k_g_combine<G_PLANE>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.bscal, d.loss,
-                     d.tot, d.flag);
-  hipLaunchKernelGGL(k_g_plane_bar, DDH_G_GRID(N, B), g.pb2, d.prm, d.bscal, g.pbar);
+  hipLaunchKernelGGL(k_g_psum, DDH_G_RGRID(N, B), g.pb2, d.prm, d.part);
+  hipLaunchKernelGGL(k_g_plane_bar, DDH_G_GRID(N, B), g.pb2, d.prm, d.minv, d.part, g.pbar);
   return hipGetLastError();
 }
+// sums of gs2, gsr, gbeta: records part[(b * g_nred(N) + blk) * 3 + q], summed by the caller
 hipError_t g_launch_totals(const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_g_tsum, DDH_G_GRID(N, B), g.gs2, g.gsr, g.gbeta, N, d.part);
-  hipLaunchKernelGGL(k_g_combine<G_TOTAL>, dim3(B), dim3(256), 0, st, d.part, g_nb(N), N, d.minv, d.scal, d.loss,
-                     d.tot, d.flag);
+  hipLaunchKernelGGL(k_g_tsum, DDH_G_RGRID(N, B), g.gs2, g.gsr, g.gbeta, N, d.part);
   return hipGetLastError();
 }
+int g_records(int N) { return g_nred(N); }
 #undef DDH_G_GRID
 #undef DDH_G_QGRID
+#undef DDH_G_RGRID
 
 }  // namespace ddh

@@ -1142,7 +1142,7 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   const int B = count;
   const size_t px = (size_t)N * N, bpx = (size_t)B * px;
   if (bpx > (size_t)INT32_MAX) return DDH_EINVAL;  // pixel indices of a batch are 32-bit
-  const int nb = (int)((px + 255) / 256);
+  const int nrec = g_records(N);
   // per-stream constants and the inverse of each pupil's moment matrix (plane fit)
   std::vector<GradPrm> prm(B);
   std::vector<double> minv(6 * (size_t)B);
@@ -1198,12 +1198,10 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   const size_t o_in = take(2 * bpx * 4);  // phi0 and phi_true of every stream, batched
   const size_t o_bf = take(12 * bpx * 4);
   const size_t o_bc = take(4 * bpx * 8);
-  const size_t o_part = take((size_t)B * nb * 3 * 8);
+  const size_t o_part = take((size_t)B * nrec * 6 * 8);
   const size_t o_prm = take(sizeof(GradPrm) * B);
   const size_t o_minv = take(sizeof(double) * 6 * B);
-  const size_t o_scal = take(2 * sizeof(GradScal) * B);
   const size_t o_loss = take(sizeof(GradLoss) * B);
-  const size_t o_tot = take(sizeof(double) * 3 * B);
   const size_t o_flag = take(sizeof(int) * B);
   const size_t o_ytab = take(sizeof(void*) * (size_t)K * B);
   char* mem = nullptr;
@@ -1217,10 +1215,7 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   GradDev dv{};
   dv.prm = (const GradPrm*)(mem + o_prm);
   dv.minv = (const double*)(mem + o_minv);
-  dv.scal = (GradScal*)(mem + o_scal);
-  dv.bscal = dv.scal + B;
   dv.loss = (GradLoss*)(mem + o_loss);
-  dv.tot = (double*)(mem + o_tot);
   dv.flag = (int*)(mem + o_flag);
   dv.part = (double*)(mem + o_part);
   const float2* const* dytab = (const float2* const*)(mem + o_ytab);
@@ -1313,13 +1308,18 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   for (int b = 0; b < B; ++b)
     if (launch_copy(d_phi0[b], g.pbar + b * px, (long long)px, st) != hipSuccess) return fail(DDH_EDEVICE);
   std::vector<GradLoss> lo(B);
-  std::vector<double> tot(3 * (size_t)B);
+  std::vector<double> rec(3 * (size_t)B * nrec);
   std::vector<int> flag(B);
   if (hipMemcpyAsync(lo.data(), dv.loss, sizeof(GradLoss) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(tot.data(), dv.tot, sizeof(double) * 3 * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(rec.data(), dv.part, sizeof(double) * rec.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(flag.data(), dv.flag, sizeof(int) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(DDH_EDEVICE);
+  // the totals' records in record order (the same for every batch composition)
+  std::vector<double> tot(3 * (size_t)B, 0.0);
+  for (int b = 0; b < B; ++b)
+    for (int r = 0; r < nrec; ++r)
+      for (int q = 0; q < 3; ++q) tot[3 * b + q] += rec[((size_t)b * nrec + r) * 3 + q];
   int res = DDH_OK;
   for (int b = 0; b < B; ++b) {
     out[b].loss = lo[b].loss;
