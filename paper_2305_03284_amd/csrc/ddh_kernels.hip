@@ -1922,7 +1922,7 @@ __global__ __launch_bounds__(256) void k_g_data(const float2* yh, const float* p
 // colour pass C of the r M-step, out of place (rin -> rout): one thread per
 // quad updates its colour-C pixel and copies the other three
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* s, const GradPrm* Pd, float* rout) {
+__device__ __forceinline__ void g_rpass_body(const float* rin, const float* s, const GradPrm* Pd, float* rout) {
   const GradPrm P = Pd[blockIdx.y];
   int qi, qj;
   if (!g_quad(qi, qj, P.N)) return;
@@ -1946,7 +1946,7 @@ __global__ __launch_bounds__(256) void k_g_rpass(const float* rin, const float* 
 }
 // colour pass C of the phi M-step, out of place, one thread per quad
 template <int C>
-__global__ __launch_bounds__(256) void k_g_ppass(const float* pin, const float* kap, const float* tth,
+__device__ __forceinline__ void g_ppass_body(const float* pin, const float* kap, const float* tth,
                                                  const GradPrm* Pd, float* pout) {
   const GradPrm P = Pd[blockIdx.y];
   int qi, qj;
@@ -2009,7 +2009,7 @@ __global__ __launch_bounds__(256) void k_g_loss_bar(const float* phi, const floa
 // One thread per quad; kbar and tbar are assigned (every pixel is of exactly
 // one colour, so the four passes write each once).
 template <int C>
-__global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float* pout, const float* kap,
+__device__ __forceinline__ void g_pback_a_body(const float* pin, const float* pout, const float* kap,
                                                    const float* tth, const GradPrm* Pd, float* pbar, float* em,
                                                    float* kbar, float* tbar, float* gbeta) {
   const GradPrm P = Pd[blockIdx.y];
@@ -2047,7 +2047,7 @@ __global__ __launch_bounds__(256) void k_g_pback_a(const float* pin, const float
   tbar[p] = tb;
 }
 // part b: pupil pixels gather em of their colour-C pupil neighbours
-__global__ __launch_bounds__(256) void k_g_pback_b(const float* em, const GradPrm* Pd, float* pbar) {
+__device__ __forceinline__ void g_pback_b_body(const float* em, const GradPrm* Pd, float* pbar) {
   const GradPrm P = Pd[blockIdx.y];
   int i, j;
   if (!g_pix(i, j, P.N)) return;
@@ -2121,7 +2121,7 @@ __device__ __forceinline__ void g_shape(float d, const GradPrm& P, float& sh, fl
 // thread per quad; Abar and Bbar are written at colour-C pixels only (part b
 // reads nothing else) and sbar is assigned (each pixel once over the passes).
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float* rout, const float* s,
+__device__ __forceinline__ void g_rback_a_body(const float* rin, const float* rout, const float* s,
                                                    const GradPrm* Pd, float* rbar, float* sbar, float* Abar,
                                                    float* Bbar, float* gsr) {
   const GradPrm P = Pd[blockIdx.y];
@@ -2177,7 +2177,7 @@ __global__ __launch_bounds__(256) void k_g_rback_a(const float* rin, const float
 }
 // part b: every pixel not of colour C gathers from its colour-C neighbours
 template <int C>
-__global__ __launch_bounds__(256) void k_g_rback_b(const float* rin, const float* Abar, const float* Bbar,
+__device__ __forceinline__ void g_rback_b_body(const float* rin, const float* Abar, const float* Bbar,
                                                    const GradPrm* Pd, float* rbar) {
   const GradPrm P = Pd[blockIdx.y];
   int i, j;
@@ -2260,6 +2260,31 @@ __global__ __launch_bounds__(256) void k_g_plane_bar(const float* pb2, const Gra
   pbar[p] = in_pupil(i, j, P.N, P.d2) ? pb2[p] - plane_val(sc[0], sc[1], sc[2], i, j, P.N) : 0.f;
 }
 
+// The r and phi sweeps are independent of each other (the phi passes read
+// only kappa and theta~, fixed for the sweep), so pass C of both runs in one
+// launch, forward and reversed.
+template <int C>
+__global__ __launch_bounds__(256) void k_g_pass(const float* rin, const float* s, const float* pin, const float* kap,
+                                                const float* tth, const GradPrm* Pd, float* rout, float* pout) {
+  g_rpass_body<C>(rin, s, Pd, rout);
+  g_ppass_body<C>(pin, kap, tth, Pd, pout);
+}
+template <int C>
+__global__ __launch_bounds__(256) void k_g_back_a(const float* pin, const float* pout, const float* kap,
+                                                  const float* tth, const float* rin, const float* rout,
+                                                  const float* s, const GradPrm* Pd, float* pbar, float* em,
+                                                  float* kbar, float* tbar, float* gbeta, float* rbar, float* sbar,
+                                                  float* Abar, float* Bbar, float* gsr) {
+  g_pback_a_body<C>(pin, pout, kap, tth, Pd, pbar, em, kbar, tbar, gbeta);
+  g_rback_a_body<C>(rin, rout, s, Pd, rbar, sbar, Abar, Bbar, gsr);
+}
+template <int C>
+__global__ __launch_bounds__(256) void k_g_back_b(const float* em, const float* rin, const float* Abar,
+                                                  const float* Bbar, const GradPrm* Pd, float* pbar, float* rbar) {
+  g_pback_b_body(em, Pd, pbar);
+  g_rback_b_body<C>(rin, Abar, Bbar, Pd, rbar);
+}
+
 #define DDH_G_GRID(N, B) dim3(((N) * (N) + 255) / 256, (B)), dim3(256), 0, st
 #define DDH_G_QGRID(N, B) dim3(((N) * (N) / 4 + 255) / 256, (B)), dim3(256), 0, st
 #define DDH_G_RGRID(N, B) dim3(g_nred(N), (B)), dim3(256), 0, st
@@ -2273,14 +2298,10 @@ hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hi
   e = launch_fft2(N, B, a.mu, a.z, a.work, a.tw, 0, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N, B), a.yh, a.phip, a.z, d.prm, a.kap, a.tth);
-  hipLaunchKernelGGL(k_g_rpass<0>, DDH_G_QGRID(N, B), a.rs[0], a.s, d.prm, a.rs[1]);
-  hipLaunchKernelGGL(k_g_rpass<1>, DDH_G_QGRID(N, B), a.rs[1], a.s, d.prm, a.rs[2]);
-  hipLaunchKernelGGL(k_g_rpass<2>, DDH_G_QGRID(N, B), a.rs[2], a.s, d.prm, a.rs[3]);
-  hipLaunchKernelGGL(k_g_rpass<3>, DDH_G_QGRID(N, B), a.rs[3], a.s, d.prm, a.rs[4]);
-  hipLaunchKernelGGL(k_g_ppass<0>, DDH_G_QGRID(N, B), a.phip, a.kap, a.tth, d.prm, a.ps[1]);
-  hipLaunchKernelGGL(k_g_ppass<1>, DDH_G_QGRID(N, B), a.ps[1], a.kap, a.tth, d.prm, a.ps[2]);
-  hipLaunchKernelGGL(k_g_ppass<2>, DDH_G_QGRID(N, B), a.ps[2], a.kap, a.tth, d.prm, a.ps[3]);
-  hipLaunchKernelGGL(k_g_ppass<3>, DDH_G_QGRID(N, B), a.ps[3], a.kap, a.tth, d.prm, a.ps[4]);
+  hipLaunchKernelGGL(k_g_pass<0>, DDH_G_QGRID(N, B), a.rs[0], a.s, a.phip, a.kap, a.tth, d.prm, a.rs[1], a.ps[1]);
+  hipLaunchKernelGGL(k_g_pass<1>, DDH_G_QGRID(N, B), a.rs[1], a.s, a.ps[1], a.kap, a.tth, d.prm, a.rs[2], a.ps[2]);
+  hipLaunchKernelGGL(k_g_pass<2>, DDH_G_QGRID(N, B), a.rs[2], a.s, a.ps[2], a.kap, a.tth, d.prm, a.rs[3], a.ps[3]);
+  hipLaunchKernelGGL(k_g_pass<3>, DDH_G_QGRID(N, B), a.rs[3], a.s, a.ps[3], a.kap, a.tth, d.prm, a.rs[4], a.ps[4]);
   return hipGetLastError();
 }
 hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d, int N, int B, float* pbar,
@@ -2294,23 +2315,17 @@ hipError_t g_launch_loss(const float* phi, const float* ptrue, const GradDev& d,
 hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B, hipStream_t st) {
   // kbar, tbar (phi passes) and sbar (r passes) are assigned at every pixel
   // by the four passes, so they need no clearing
-  // phi sweep reversed (ps[c] = input of pass c, ps[0] = phi')
+  // both sweeps reversed, pass by pass (ps[c], rs[c] = inputs of pass c, ps[0] = phi')
   const float* ps0 = a.phip;
-#define DDH_PB(C)                                                                                         \
-  hipLaunchKernelGGL(k_g_pback_a<C>, DDH_G_QGRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, \
-                     d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta);                                        \
-  hipLaunchKernelGGL(k_g_pback_b, DDH_G_GRID(N, B), g.em, d.prm, g.pbar);
-  DDH_PB(3) DDH_PB(2) DDH_PB(1) DDH_PB(0)
-#undef DDH_PB
+#define DDH_BK(C)                                                                                                 \
+  hipLaunchKernelGGL(k_g_back_a<C>, DDH_G_QGRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, a.rs[C], \
+                     a.rs[C + 1], a.s, d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta, g.rbar, g.sbar, g.Abar,      \
+                     g.Bbar, g.gsr);                                                                             \
+  hipLaunchKernelGGL(k_g_back_b<C>, DDH_G_GRID(N, B), g.em, a.rs[C], g.Abar, g.Bbar, d.prm, g.pbar, g.rbar);
+  DDH_BK(3) DDH_BK(2) DDH_BK(1) DDH_BK(0)
+#undef DDH_BK
   hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, g.pbar, d.prm, g.pb2,
                      g.zbar, g.gs2);
-  // r sweep reversed (rs[c] = input of pass c)
-#define DDH_RB(C)                                                                                                \
-  hipLaunchKernelGGL(k_g_rback_a<C>, DDH_G_QGRID(N, B), a.rs[C], a.rs[C + 1], a.s, d.prm, g.rbar, g.sbar, g.Abar, \
-                     g.Bbar, g.gsr);                                                                            \
-  hipLaunchKernelGGL(k_g_rback_b<C>, DDH_G_GRID(N, B), a.rs[C], g.Abar, g.Bbar, d.prm, g.rbar);
-  DDH_RB(3) DDH_RB(2) DDH_RB(1) DDH_RB(0)
-#undef DDH_RB
   // z = F mu  ->  mubar = F^H zbar
   hipError_t e = launch_fft2(N, B, g.zbar, g.mubar, a.work, a.tw, 1, st);
   if (e != hipSuccess) return e;
