@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     p.add_argument("--graph", action="store_true", help="replay the batched step as a HIP graph (eager launches "
                    "are the default: they measured faster)")
-    p.add_argument("--lanes", type=int, default=1, help="split the batch into this many HIP streams (1-8)")
+    p.add_argument("--lanes", type=int, default=0, help="HIP streams of the batch: 0 = one per distinct N (default), "
+                   "1-8 = that many, balanced by pixels")
     p.add_argument("--serve", action="store_true", help="instead: the continuous-batching request loop (32 streams "
                    "at N in {128,256}, Poisson arrivals) against the one-frame-at-a-time loop")
     p.add_argument("--serve-rate", type=float, default=2000.0, help="aggregate frame arrival rate (Hz)")
@@ -533,7 +534,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "streams": S, "N": args.N if args.workload == "uniform" else "mixed",
                    "n_k": 1, "pixels_per_step": px_total, "frames_cycled": args.frames,
-                   "launch": "graph" if args.graph else "eager", "lanes": args.lanes,
+                   "launch": "graph" if args.graph else "eager", "lanes": "one per N" if args.lanes == 0 else args.lanes,
                    "tiles": {str(k): v for k, v in tiles.items()}},
     }
 

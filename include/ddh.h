@@ -160,13 +160,15 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
 /* Group `count` streams (any mix of N) so that one call advances all of them
  * by one frame.  Streams keep their own state and numerics: a stream gives
  * the same result alone and in any batch.  flags: DDH_BATCH_GRAPH captures the
- * per-frame launch sequence in a HIP graph on first use; DDH_BATCH_LANES(n)
- * (n = 1..8) splits the streams into n lanes balanced by pixel count whose
- * launch chains run on n internal HIP streams forked from and joined back
- * into the caller's stream (a graph then has n parallel branches; on the
- * 64 x N=256 workload two or more lanes measured slower than one).  All n_k
- * must be equal.  The batch does not own the streams; destroy the batch
- * before its streams. */
+ * per-frame launch sequence in a HIP graph on first use.  The streams are
+ * split into lanes whose launch chains run on internal HIP streams forked
+ * from and joined back into the caller's stream (a graph then has parallel
+ * branches): by default (lane count 0) one lane per distinct N, so that the
+ * launches of different sizes overlap (a uniform batch has one lane);
+ * DDH_BATCH_LANES(n) (n = 1..8) instead splits the streams into n lanes
+ * balanced by pixel count (on the 64 x N=256 and mixed-size workloads two or
+ * more such lanes measured slower than one).  All n_k must be equal.  The
+ * batch does not own the streams; destroy the batch before its streams. */
 #define DDH_BATCH_GRAPH 1
 #define DDH_BATCH_LANES(n) (((n) & 0xff) << 8)
 int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);

@@ -244,11 +244,11 @@ class Stream:
 class Batch:
     """Several streams advanced together by one call per frame."""
 
-    def __init__(self, streams, graph: bool = True, lanes: int = 1):
+    def __init__(self, streams, graph: bool = True, lanes: int = 0):
         self.streams = list(streams)
         arr = (ctypes.c_void_p * len(self.streams))(*[s.handle.value for s in self.streams])
         h = ctypes.c_void_p()
-        flags = (DDH_BATCH_GRAPH if graph else 0) | ((int(lanes) & 0xff) << 8)
+        flags = (DDH_BATCH_GRAPH if graph else 0) | ((int(lanes) & 0xff) << 8)  # lanes 0: one per distinct N
         _check(lib().ddh_batch_create(arr, len(self.streams), flags, ctypes.byref(h)), "ddh_batch_create")
         self._h = h
         self._ptrs = (ctypes.c_void_p * len(self.streams))()

@@ -677,8 +677,14 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
       if (streams[j] == streams[i]) return DDH_EINVAL;
   }
   const int nl = (flags >> 8) & 0xff;
-  const int nlanes = std::max(1, std::min(nl == 0 ? 1 : nl, std::min(count, 8)));
   if (nl > 8) return DDH_EINVAL;
+  std::vector<int> sizes;  // distinct N, largest first
+  for (int i = 0; i < count; ++i)
+    if (std::find(sizes.begin(), sizes.end(), streams[i]->N) == sizes.end()) sizes.push_back(streams[i]->N);
+  std::sort(sizes.rbegin(), sizes.rend());
+  // lane count 0: one lane per distinct N (a uniform batch has one lane)
+  const bool by_n = nl == 0;
+  const int nlanes = by_n ? (int)sizes.size() : std::min(nl, std::min(count, 8));
   ddh_batch_t b = new ddh_batch_s();
   b->streams.assign(streams, streams + count);
   b->total = count;
@@ -694,7 +700,8 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
   std::vector<long long> load(nlanes, 0);
   std::vector<std::vector<int>> members(nlanes);
   for (int i : idx) {
-    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    const int l = by_n ? (int)(std::find(sizes.begin(), sizes.end(), streams[i]->N) - sizes.begin())
+                       : (int)(std::min_element(load.begin(), load.end()) - load.begin());
     members[l].push_back(i);
     load[l] += (long long)streams[i]->N * streams[i]->N;
   }

@@ -550,8 +550,9 @@ def test_autotune_installs_a_valid_tiling():
         D.set_tiles(N, (3, 8, 16, 16))
 
 
-@pytest.mark.parametrize("lanes,graph", [(2, False), (3, True), (4, True)])
+@pytest.mark.parametrize("lanes,graph", [(0, False), (0, True), (2, False), (3, True), (4, True)])
 def test_batch_lanes_equal_single_lane(lanes, graph):
+    """lanes 0 is one lane per distinct N (the default), n >= 1 pixel-balanced"""
     D = _ddh()
     specs = _mixed_specs()
     sims = [synth.Stream(sp) for sp in specs]
