@@ -212,7 +212,9 @@ int ddh_server_create(int max_streams, ddh_server_t* out);
 int ddh_stream_bytes(int N, unsigned long long* bytes);
 int ddh_server_destroy(ddh_server_t s);
 
-/* One DDH frame on each of `count` (0..max_streams) distinct streams.
+/* One DDH frame on each of `count` (0..max_streams) distinct streams.  The
+ * frames of each N run on an internal HIP stream of the server, forked from
+ * and joined back into hip_stream, so that different sizes overlap.
  * streams: host array of handles; y: host array of device pointers to their
  * frames (N*N complex64 each).  Both host arrays may be reused once the call
  * returns.  DDH_EINVAL for a repeated stream or a null frame. */

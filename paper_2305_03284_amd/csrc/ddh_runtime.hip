@@ -214,6 +214,10 @@ struct ddh_server_s {
   std::vector<const float2*> ys;
   std::vector<int> curs;
   std::vector<StreamDesc*> ds;
+  // one internal HIP stream per N group of a call, forked from and joined
+  // back into the caller's stream
+  hipStream_t lane[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
   bool alive() const { return magic == kAlive; }
 };
 
@@ -903,9 +907,20 @@ int ddh_server_create(int max_streams, ddh_server_t* out) {
   v->device = dev;
   v->max = max_streams;
   hipError_t e = hipMalloc(&v->list, sizeof(StreamDesc*) * max_streams);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&v->fork, hipEventDisableTiming);
+  for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+    e = hipStreamCreateWithFlags(&v->lane[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&v->join[l], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
+    for (int l = 0; l < 4; ++l) {
+      if (v->lane[l]) (void)hipStreamDestroy(v->lane[l]);
+      if (v->join[l]) (void)hipEventDestroy(v->join[l]);
+    }
+    if (v->fork) (void)hipEventDestroy(v->fork);
+    if (v->list) (void)hipFree(v->list);
     delete v;
-    return hip_fail(e, "hipMalloc(server)");
+    return hip_fail(e, "ddh_server_create");
   }
   *out = v;
   return DDH_OK;
@@ -916,6 +931,11 @@ int ddh_server_destroy(ddh_server_t v) {
   if (!v->alive()) return DDH_ESTATE;
   set_device_of(v->device);
   (void)hipDeviceSynchronize();
+  for (int l = 0; l < 4; ++l) {
+    (void)hipStreamDestroy(v->lane[l]);
+    (void)hipEventDestroy(v->join[l]);
+  }
+  (void)hipEventDestroy(v->fork);
   (void)hipFree(v->list);
   v->magic = kDead;
   delete v;
@@ -969,9 +989,22 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
       }
       groups.push_back(g);
     }
-    int rc = enqueue_frame(v->list + p0, groups, p1 - p0, n_k, 1, st, NoTiming{}, v->ys.data() + p0,
-                           v->curs.data() + p0, v->ds.data() + p0);
-    if (rc != DDH_OK) return rc;
+    if (groups.size() == 1) {
+      int rc = enqueue_frame(v->list + p0, groups, p1 - p0, n_k, 1, st, NoTiming{}, v->ys.data() + p0,
+                             v->curs.data() + p0, v->ds.data() + p0);
+      if (rc != DDH_OK) return rc;
+    } else {  // the N groups (at most 4) on their own lanes, so that their launches overlap
+      DDH_CHECK(hipEventRecord(v->fork, st));
+      for (size_t l = 0; l < groups.size(); ++l) {
+        DDH_CHECK(hipStreamWaitEvent(v->lane[l], v->fork, 0));
+        const std::vector<Group> one{groups[l]};
+        int rc = enqueue_frame(v->list + p0, one, groups[l].count, n_k, 1, v->lane[l], NoTiming{},
+                               v->ys.data() + p0, v->curs.data() + p0, v->ds.data() + p0);
+        if (rc != DDH_OK) return rc;
+        DDH_CHECK(hipEventRecord(v->join[l], v->lane[l]));
+      }
+      for (size_t l = 0; l < groups.size(); ++l) DDH_CHECK(hipStreamWaitEvent(st, v->join[l], 0));
+    }
     p0 = p1;
   }
   for (int i = 0; i < count; ++i) {
