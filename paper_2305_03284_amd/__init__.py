@@ -89,6 +89,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_03284_amd.build`")
+        # torch first: the library's HIP runtime dependency then resolves to
+        # the runtime torch has already loaded, so the process holds one HIP
+        # runtime (loaded the other way round there are two, and the second
+        # to initialise finds no device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

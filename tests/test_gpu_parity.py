@@ -504,6 +504,28 @@ def test_full_size_batch_sampled_against_oracle():
     b.close()
 
 
+def test_full_size_mixed_batch_sampled_against_oracle():
+    """The uneven batch as timed by the benchmark's mixed workload (64 streams,
+    N in {128, 256, 512} at 2:5:1, one lane per N, eager): one sampled stream
+    of each size against the oracle frame by frame."""
+    D = _ddh()
+    specs = synth.batch_specs(count=64, config_id=2)
+    sims = [synth.Stream(sp) for sp in specs]
+    pairs = [make_pair(sp.N, sm.sigma_w2) for sp, sm in zip(specs, sims)]
+    streams = [D.Stream(sp.N, pairs[i][1]) for i, sp in enumerate(specs)]
+    b = D.Batch(streams, graph=False)
+    sample = [next(i for i, sp in enumerate(specs) if sp.N == n) for n in (128, 256, 512)]
+    orc = {i: (np.zeros((specs[i].N,) * 2), np.zeros((specs[i].N,) * 2)) for i in sample}
+    for n in range(2):
+        say(f"full-size mixed batch frame {n}")
+        b.step([dev(sm.frame(n)) for sm in sims])
+        for i in sample:
+            a = O.aperture(specs[i].N)
+            orc[i] = O.ddh_frame(*orc[i], sims[i].frame(n).astype(np.complex128), a, pairs[i][0])
+            compare(f"stream {i} N={specs[i].N} frame {n}", *state(streams[i]), *orc[i], a)
+    b.close()
+
+
 # ----------------------------------------------------------------------------- tiling
 
 def _run_frames(D, N, gp, frames):
