@@ -240,7 +240,9 @@ int ddh_server_step(ddh_server_t s, const ddh_stream_t* streams, const void* con
  * branch the forward took (floors, the root choice, the phase wrap); the
  * QGGMRF weight's unbounded derivative at zero difference is taken as zero.
  * Parameters as for ddh_init_stream, with n_k = 1 and qg_p = 2 (DDH_EINVAL
- * otherwise).  Allocates its workspace, synchronises hip_stream.  DDH_EDATA
+ * otherwise).  Its workspace is allocated on the first call on a device,
+ * grown when a call needs more and kept until the process ends; calls on
+ * one device take turns on it (each returns synchronised with hip_stream).  DDH_EDATA
  * if a frame cannot be normalised or the loss is zero. */
 typedef struct {
   double loss;

@@ -1244,12 +1244,30 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   const size_t o_loss = take(sizeof(GradLoss) * B);
   const size_t o_flag = take(sizeof(int) * B);
   const size_t o_ytab = take(sizeof(void*) * (size_t)K * B);
-  char* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, off);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(grad)");
+  // the device's workspace, kept between calls and grown when too small;
+  // calls on one device take turns on it (each ends synchronised)
+  static std::mutex ws_mu[kMaxDev];
+  static char* ws_mem[kMaxDev] = {nullptr};
+  static size_t ws_cap[kMaxDev] = {0};
+  if (dev < 0 || dev >= kMaxDev) return DDH_EDEVICE;
+  std::lock_guard<std::mutex> ws_lock(ws_mu[dev]);
+  if (ws_cap[dev] < off) {
+    if (ws_mem[dev]) {
+      (void)hipFree(ws_mem[dev]);
+      ws_mem[dev] = nullptr;
+      ws_cap[dev] = 0;
+    }
+    hipError_t ea = hipMalloc(&ws_mem[dev], off);
+    if (ea != hipSuccess) {
+      ws_mem[dev] = nullptr;
+      return hip_fail(ea, "hipMalloc(grad)");
+    }
+    ws_cap[dev] = off;
+  }
+  char* mem = ws_mem[dev];
+  hipError_t e = hipSuccess;
   auto fail = [&](int code) {
     (void)hipStreamSynchronize(st);
-    (void)hipFree(mem);
     return code;
   };
   GradDev dv{};
