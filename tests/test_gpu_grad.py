@@ -193,3 +193,22 @@ def test_config3_size_smooth_prior_against_reference():
     assert _rel(g[m], gr_phi[m]) < 1e-3
     for x, y in ((gw, gr_w), (gr, gr_r), (gb, gr_b)):
         assert abs(x - y) <= 1e-3 * abs(y) + 1e-9
+
+
+def test_workspace_reuse_after_a_larger_call():
+    """The per-device workspace grows for a large call and is reused by a
+    smaller one: a small call gives bit for bit the same result before and
+    after a larger call (every array it reads is written or cleared first)."""
+    torch = _torch()
+    import paper_2305_03284_amd as D
+    st, a, frames, phi0, ptrue = _case(64, 3, seed=7)
+    prm = _params(D, 64, st)
+    fr = [torch.from_numpy(f).cuda() for f in frames]
+    p0, pt = torch.from_numpy(phi0).cuda(), torch.from_numpy(ptrue).cuda()
+    first = D.unrolled_grad(prm, fr, p0, pt, 2)
+    big, a2, frames2, phi02, ptrue2 = _case(128, 4, seed=8)
+    D.unrolled_grad(_params(D, 128, big), [torch.from_numpy(f).cuda() for f in frames2],
+                    torch.from_numpy(phi02).cuda(), torch.from_numpy(ptrue2).cuda(), 1)
+    again = D.unrolled_grad(prm, fr, p0, pt, 2)
+    assert (first[0], first[2], first[3], first[4]) == (again[0], again[2], again[3], again[4])
+    assert torch.equal(first[1], again[1])
