@@ -259,7 +259,7 @@ int ddh_unrolled_grad(const ddh_params* p, int K, const void* const* y, const fl
  * (y[b*K + k] is frame k of stream b); phi0, phi_true, d_phi0: host arrays of
  * count device pointers (N*N floats each); out: host array of count results.
  * Each stream's results are bit-identical to ddh_unrolled_grad on that stream
- * alone.  Workspace about (8 ceil(K/ckpt) + 92 ckpt + 100) bytes per pixel per
+ * alone.  Workspace about (8 ceil(K/ckpt) + 92 ckpt + 84) bytes per pixel per
  * stream.  DDH_EINVAL for mixed N or a null pointer; DDH_EDATA if a frame of
  * any stream cannot be normalised or a loss is zero (the other streams'
  * results are still written); DDH_EINVAL also if count*N*N exceeds 2^31 - 1. */

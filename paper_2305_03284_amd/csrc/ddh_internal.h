@@ -145,7 +145,7 @@ struct GradFwd {
 // adjoint work arrays (B images of N*N); gs2, gsr, gbeta accumulate per pixel
 struct GradBwd {
   float *rbar, *pbar, *pb2, *em, *kbar, *tbar, *sbar, *Abar, *Bbar;
-  float2 *zbar, *mubar, *bbar, *vbar;
+  float2 *zbar, *vbar;
   float *gs2, *gsr, *gbeta;
 };
 hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st);

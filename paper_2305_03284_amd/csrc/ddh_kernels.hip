@@ -1878,20 +1878,52 @@ __global__ __launch_bounds__(256) void k_g_prologue(const float2* const* ys, con
   phip[p] = ph;
   v[p] = vv;
 }
-// Eq. (3) and the E-step: r0, mu (into mu), s
-__global__ __launch_bounds__(256) void k_g_estep(const float* rprev, const float2* b, const GradPrm* Pd, float* r0,
-                                                 float2* mu, float* s) {
-  const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int p = g_at(i, j, P.N);
-  const float2 bv = b[p];
+// Eq. (3) and the E-step at one pixel: r0, mu, s from b and the previous r
+__device__ __forceinline__ float2 g_estep_px(float2 bv, float rprev, const GradPrm& P, float& r0, float& s) {
   const float bb = bv.x * bv.x + bv.y * bv.y;
-  const float r = rinit_of(rprev[p], bb, P.lam, P.alpha, P.fl);
+  const float r = rinit_of(rprev, bb, P.lam, P.alpha, P.fl);
   const float w = wiener_of(r, P.s2);
-  r0[p] = r;
-  mu[p] = make_float2(w * bv.x, w * bv.y);
-  s[p] = second_moment(w, bb, P.s2);
+  r0 = r;
+  s = second_moment(w, bb, P.s2);
+  return make_float2(w * bv.x, w * bv.y);
+}
+// Column pass of the frame's two DFTs with the E-step between them, as the
+// fast path's column kernel: work holds the row-transformed v; the inverse
+// column DFT gives b, the E-step mu (b, r0, mu and s are kept for the
+// adjoint), the forward column DFT of mu goes back into work (scaled by 1/N),
+// whose forward row DFT is z.  grid (N / W, streams), in place.
+template <int N, int W>
+__global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_g_col_fwd(float2* work, const float* rprev, const GradPrm* Pd,
+                                                                float2* b, float* r0, float2* mu, float* s,
+                                                                const float2* __restrict__ tw) {
+  constexpr int E = Plan<N>::E;
+  __shared__ float2 lds[N * ColLds<W>::STRIDE];
+  const GradPrm P = Pd[blockIdx.y];
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const int img = blockIdx.y * N * N;
+  const int col = blockIdx.x * W + w;
+  float2 v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = work[img + first_pos<N, +1>(i, t) * N + col];
+  ColLds<W> L{lds + w};
+  line_fft<N, +1>(v, t, L, tw);
+  const float invN = 1.0f / (float)N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int p = img + last_pos<N, +1>(i, t) * N + col;
+    const float2 bv = cscale(v[i], invN);
+    float rr, ss;
+    const float2 m = g_estep_px(bv, rprev[p], P, rr, ss);
+    b[p] = bv;
+    r0[p] = rr;
+    s[p] = ss;
+    mu[p] = m;
+    v[i] = m;
+  }
+  __syncthreads();
+  line_fft<N, -1>(v, t, L, tw);
+#pragma unroll
+  for (int i = 0; i < E; ++i) work[img + last_pos<N, -1>(i, t) * N + col] = cscale(v[i], invN);
 }
 // phase data term: kappa, theta~ on the pupil (as the fast path's second row pass)
 __device__ __forceinline__ void g_data_u(float2 h, float ph, float2 z, float& ur, float& ui) {
@@ -2202,32 +2234,61 @@ __device__ __forceinline__ void g_rback_b_body(const float* rin, const float* Ab
   }
   rbar[p] += acc;
 }
-// E-step and Eq. (3) reversed: (mubar, sbar, r0bar) -> bbar, rbar of the previous state, s2
-__global__ __launch_bounds__(256) void k_g_estep_bar(const float* rprev, const float2* b, const float* r0,
-                                                     const float2* mubar, const float* sbar, const GradPrm* Pd,
-                                                     float* rbar, float2* bbar, float* gs2) {
-  const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int p = g_at(i, j, P.N);
-  const float2 bv = b[p], mb = mubar[p];
+// E-step and Eq. (3) reversed at one pixel: (mubar, sbar, r0bar) -> bbar
+// (returned), rbar of the previous state (assigned), s2 (accumulated)
+__device__ __forceinline__ float2 g_estep_bar_px(float2 bv, float2 mb, float rprev, float r, float sb, const GradPrm& P,
+                                                 float& rbar, float& gs2) {
   const float bb = bv.x * bv.x + bv.y * bv.y;
-  const float r = r0[p], den = r + P.s2, w = r / den;
-  const float sb = sbar[p];
+  const float den = r + P.s2, w = r / den;
   const float wb = (mb.x * bv.x + mb.y * bv.y) + sb * (P.s2 + 2.0f * w * bb);
   float2 gb = make_float2(w * mb.x + 2.0f * sb * w * w * bv.x, w * mb.y + 2.0f * sb * w * w * bv.y);
-  float g2 = sb * w - wb * r / (den * den);
-  const float r0b = rbar[p] + wb * P.s2 / (den * den);
-  const float x = (1.0f - P.lam) * rprev[p] + P.lam * P.alpha * bb;
+  const float g2 = sb * w - wb * r / (den * den);
+  const float r0b = rbar + wb * P.s2 / (den * den);
+  const float x = (1.0f - P.lam) * rprev + P.lam * P.alpha * bb;
   float rp = 0.f;
   if (x > P.fl) {
     rp = (1.0f - P.lam) * r0b;
     gb.x += 2.0f * P.lam * P.alpha * r0b * bv.x;
     gb.y += 2.0f * P.lam * P.alpha * r0b * bv.y;
   }
-  rbar[p] = rp;
-  bbar[p] = gb;
-  gs2[p] += g2;
+  rbar = rp;
+  gs2 += g2;
+  return gb;
+}
+// Column pass of the adjoint's two DFTs with the E-step adjoint between
+// them: work holds the row-transformed zbar; the inverse column DFT gives
+// mubar = F^H zbar, the E-step adjoint bbar, whose forward column DFT goes
+// back into work (scaled by 1/N); its forward row DFT is vbar = F bbar.
+// grid (N / W, streams), in place.
+template <int N, int W>
+__global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_g_col_bwd(float2* work, const float* rprev, const float2* b,
+                                                                const float* r0, const float* sbar,
+                                                                const GradPrm* Pd, float* rbar, float* gs2,
+                                                                const float2* __restrict__ tw) {
+  constexpr int E = Plan<N>::E;
+  __shared__ float2 lds[N * ColLds<W>::STRIDE];
+  const GradPrm P = Pd[blockIdx.y];
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const int img = blockIdx.y * N * N;
+  const int col = blockIdx.x * W + w;
+  float2 v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = work[img + first_pos<N, +1>(i, t) * N + col];
+  ColLds<W> L{lds + w};
+  line_fft<N, +1>(v, t, L, tw);
+  const float invN = 1.0f / (float)N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int p = img + last_pos<N, +1>(i, t) * N + col;
+    float rb = rbar[p], g2 = gs2[p];
+    v[i] = g_estep_bar_px(b[p], cscale(v[i], invN), rprev[p], r0[p], sbar[p], P, rb, g2);
+    rbar[p] = rb;
+    gs2[p] = g2;
+  }
+  __syncthreads();
+  line_fft<N, -1>(v, t, L, tw);
+#pragma unroll
+  for (int i = 0; i < E; ++i) work[img + last_pos<N, -1>(i, t) * N + col] = cscale(v[i], invN);
 }
 // back-projection reversed: phi' adjoint += Im(conj(vbar) v), v = a exp(-j phi') yhat
 __global__ __launch_bounds__(256) void k_g_bp_bar(const float2* vbar, const float2* yh, const float* phip,
@@ -2289,13 +2350,44 @@ __global__ __launch_bounds__(256) void k_g_back_b(const float* em, const float* 
 #define DDH_G_QGRID(N, B) dim3(((N) * (N) / 4 + 255) / 256, (B)), dim3(256), 0, st
 #define DDH_G_RGRID(N, B) dim3(g_nred(N), (B)), dim3(256), 0, st
 
+// the frame's DFT pair with the E-step (forward) or its adjoint (backward)
+// between the column passes: row pass, fused column pass, row pass
+template <int N>
+static hipError_t g_dfts_fwd_n(const GradFwd& a, const GradDev& d, int B, hipStream_t st) {
+  constexpr int T = N / Plan<N>::E;
+  constexpr int L = 256 / T > N ? N : 256 / T;
+  hipLaunchKernelGGL((k_row_plain<N, L, +1>), dim3(N / L, B), dim3(L * T), 0, st, a.v, a.work, a.tw);
+  hipLaunchKernelGGL((k_g_col_fwd<N, L>), dim3(N / L, B), dim3(L * T), 0, st, a.work, a.r_in, d.prm, a.b, a.rs[0],
+                     a.mu, a.s, a.tw);
+  hipLaunchKernelGGL((k_row_plain<N, L, -1>), dim3(N / L, B), dim3(L * T), 0, st, a.work, a.z, a.tw);
+  return hipGetLastError();
+}
+template <int N>
+static hipError_t g_dfts_bwd_n(const GradFwd& a, const GradBwd& g, const GradDev& d, int B, hipStream_t st) {
+  constexpr int T = N / Plan<N>::E;
+  constexpr int L = 256 / T > N ? N : 256 / T;
+  hipLaunchKernelGGL((k_row_plain<N, L, +1>), dim3(N / L, B), dim3(L * T), 0, st, g.zbar, a.work, a.tw);
+  hipLaunchKernelGGL((k_g_col_bwd<N, L>), dim3(N / L, B), dim3(L * T), 0, st, a.work, a.r_in, a.b, a.rs[0], g.sbar,
+                     d.prm, g.rbar, g.gs2, a.tw);
+  hipLaunchKernelGGL((k_row_plain<N, L, -1>), dim3(N / L, B), dim3(L * T), 0, st, a.work, g.vbar, a.tw);
+  return hipGetLastError();
+}
+static hipError_t g_launch_dfts_fwd(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st) {
+#define DDH_X(NN) return g_dfts_fwd_n<NN>(a, d, B, st)
+  DDH_DISPATCH_N(N, DDH_X)
+#undef DDH_X
+}
+static hipError_t g_launch_dfts_bwd(const GradFwd& a, const GradBwd& g, const GradDev& d, int N, int B,
+                                    hipStream_t st) {
+#define DDH_X(NN) return g_dfts_bwd_n<NN>(a, g, d, B, st)
+  DDH_DISPATCH_N(N, DDH_X)
+#undef DDH_X
+}
+
 hipError_t g_launch_forward(const GradFwd& a, const GradDev& d, int N, int B, hipStream_t st) {
   hipLaunchKernelGGL(k_g_stats, DDH_G_RGRID(N, B), a.y, a.phi_in, d.prm, d.part);
   hipLaunchKernelGGL(k_g_prologue, DDH_G_GRID(N, B), a.y, a.phi_in, d.prm, d.minv, d.part, d.flag, a.yh, a.phip, a.v);
-  hipError_t e = launch_fft2(N, B, a.v, a.b, a.work, a.tw, 1, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_estep, DDH_G_GRID(N, B), a.r_in, a.b, d.prm, a.rs[0], a.mu, a.s);
-  e = launch_fft2(N, B, a.mu, a.z, a.work, a.tw, 0, st);
+  hipError_t e = g_launch_dfts_fwd(a, d, N, B, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_data, DDH_G_GRID(N, B), a.yh, a.phip, a.z, d.prm, a.kap, a.tth);
   hipLaunchKernelGGL(k_g_pass<0>, DDH_G_QGRID(N, B), a.rs[0], a.s, a.phip, a.kap, a.tth, d.prm, a.rs[1], a.ps[1]);
@@ -2326,13 +2418,8 @@ hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& 
 #undef DDH_BK
   hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, g.pbar, d.prm, g.pb2,
                      g.zbar, g.gs2);
-  // z = F mu  ->  mubar = F^H zbar
-  hipError_t e = launch_fft2(N, B, g.zbar, g.mubar, a.work, a.tw, 1, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_g_estep_bar, DDH_G_GRID(N, B), a.r_in, a.b, a.rs[0], g.mubar, g.sbar, d.prm, g.rbar, g.bbar,
-                     g.gs2);
-  // b = F^H v  ->  vbar = F bbar
-  e = launch_fft2(N, B, g.bbar, g.vbar, a.work, a.tw, 0, st);
+  // z = F mu -> mubar = F^H zbar; E-step reversed; b = F^H v -> vbar = F bbar
+  hipError_t e = g_launch_dfts_bwd(a, g, d, N, B, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_g_bp_bar, DDH_G_GRID(N, B), g.vbar, a.yh, a.phip, d.prm, g.pb2);
   // tip/tilt removal reversed: the plane of pb2 over the pupil, subtracted

@@ -5,6 +5,7 @@
 #include "ddh_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -1160,6 +1161,34 @@ int ddh_fft2(int N, int count, const void* in, void* out, void* work, int invers
 
 
 // ------------------------------------------------------- differentiation
+// Inverse of the pupil's plane-fit moment matrix (symmetric: 00 01 02 11 12
+// 22), computed once per (N, diameter^2) and kept.
+static std::array<double, 6> pupil_moment_inverse(int N, float d2) {
+  static std::mutex mu;
+  static std::map<std::pair<int, float>, std::array<double, 6>> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(N, d2);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  const double c = 0.5 * (N - 1);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
+      if ((float)(di * di + dj * dj) > d2) continue;
+      const double a = i - c, e = j - c;
+      m[0] += 1, m[1] += a, m[2] += e, m[3] += a * a, m[4] += a * e, m[5] += e * e;
+    }
+  const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+  const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+  const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+  const double det = a00 * c00 + a01 * c01 + a02 * c02;
+  std::array<double, 6> inv{};
+  if (det != 0.0) inv = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
+  cache[key] = inv;
+  return inv;
+}
+
 int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* const* y, const float* const* phi0,
                             const float* const* phi_true, int ckpt, float* const* d_phi0, ddh_grad_out* out,
                             void* hip_stream) {
@@ -1201,21 +1230,8 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
     P.qop = q.qg_q / q.qg_p;
     P.beta = q.beta_phi;
     P.sig_r = q.qg_sigma;
-    double m[6] = {0, 0, 0, 0, 0, 0};
-    const double c = 0.5 * (N - 1);
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) {
-        const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
-        if ((float)(di * di + dj * dj) > P.d2) continue;
-        const double a = i - c, e = j - c;
-        m[0] += 1, m[1] += a, m[2] += e, m[3] += a * a, m[4] += a * e, m[5] += e * e;
-      }
-    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
-    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
-    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
-    const double det = a00 * c00 + a01 * c01 + a02 * c02;
-    const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
-    for (int k = 0; k < 6; ++k) minv[6 * (size_t)b + k] = det != 0.0 ? inv[k] : 0.0;
+    const std::array<double, 6> inv = pupil_moment_inverse(N, P.d2);
+    for (int k = 0; k < 6; ++k) minv[6 * (size_t)b + k] = inv[k];
   }
   // frame tables, frame-major: ytab[k * B + b]
   std::vector<const void*> ytab((size_t)K * B);
@@ -1237,7 +1253,7 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
   const size_t o_r0 = take(bpx * 4);
   const size_t o_in = take(2 * bpx * 4);  // phi0 and phi_true of every stream, batched
   const size_t o_bf = take(12 * bpx * 4);
-  const size_t o_bc = take(4 * bpx * 8);
+  const size_t o_bc = take(2 * bpx * 8);
   const size_t o_part = take((size_t)B * nrec * 6 * 8);
   const size_t o_prm = take(sizeof(GradPrm) * B);
   const size_t o_minv = take(sizeof(double) * 6 * B);
@@ -1312,7 +1328,7 @@ int ddh_unrolled_grad_batch(const ddh_params* p, int count, int K, const void* c
                       &g.gs2, &g.gsr, &g.gbeta};
     for (int q = 0; q < 12; ++q) *fp[q] = f + q * bpx;
     float2* c = (float2*)(mem + o_bc);
-    g.zbar = c, g.mubar = c + bpx, g.bbar = c + 2 * bpx, g.vbar = c + 3 * bpx;
+    g.zbar = c, g.vbar = c + bpx;
   }
   if (launch_fill_zero(rzero, (long long)bpx, st) != hipSuccess ||
       launch_fill_zero((float*)(mem + o_bf), 12 * (long long)bpx, st) != hipSuccess ||
