@@ -32,6 +32,10 @@ struct StreamDesc {
   float* bb;           // |b|^2 from the column pass
   float* part;         // stats partials, PART_STRIDE floats per stats block
   float* scal;         // SC_COUNT floats
+  // per pixel: prior weight of the pupil neighbours in twelfths (bits 0-3:
+  // 2 per edge and 1 per diagonal neighbour inside the pupil) and the
+  // in-pupil flag (bit 4); zero off the pupil.  Written once at creation.
+  const unsigned char* geo;
   int N;
   int cur;             // index of the current state buffer at the start of a frame
   float pupil_d2;      // diameter^2 (pixel (i,j) in pupil iff (2i-N+1)^2+(2j-N+1)^2 <= d2)

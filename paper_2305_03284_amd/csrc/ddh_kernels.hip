@@ -991,6 +991,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const float4* pin4 = reinterpret_cast<const float4*>(pin);
   const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
   const auto ktp = glb(D.T);
+  const unsigned char* geop = glb(D.geo);
   float4 gr[SR], gb[SR], gph[SR];
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
@@ -1007,9 +1008,13 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   // per own pixel, one packed word: LDS offset (bits 0-15), neighbour mask
   // (16-19), pupil-neighbour weight in twelfths (20-23), in-pupil flag (24);
   // -1 when the pixel is off the grid or beyond this pass.  Then kappa and
-  // theta~.  Tiles away from the grid border have every neighbour.
+  // theta~.  Tiles away from the grid border have every neighbour.  The
+  // pupil bits come from the stream's per-pixel geometry bytes, and (kappa,
+  // theta~) is read at every own pixel ((0, 0) off the pupil); both loads are
+  // unconditional (a slot without a pixel reads pixel 0) and the bytes are
+  // merged once every load has arrived.
   const bool border = ti == 0 || ti == TPR - 1 || tj == 0 || tj == TPC - 1;
-  int opk[SLOTS];
+  int opk[SLOTS], ogeo[SLOTS];
   float okap[SLOTS], ott[SLOTS];
   static_for<0, 4>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
@@ -1021,20 +1026,12 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
       const int li = G::li0(c) + 2 * u, lj = G::lj0(c) + 2 * (idx - u * G::nv(c));
       const int gi = gi0 + li, gj = gj0 + lj;
       const bool own = idx < G::n(c) && (!border || (gi >= 0 && gi < N && gj >= 0 && gj < N));
-      int pk = (li * RW + lj) | ((border ? nb_mask(gi, gj, N) : NB_ALL) << 16);
-      okap[slot] = 0.f;
-      ott[slot] = 0.f;
-      const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
-      const int r2 = __mul24(di, di) + __mul24(dj, dj);
-      if (own && (float)r2 <= d2) {
-        const float2 kt = ktp[gi * N + gj];
-        okap[slot] = kt.x;
-        ott[slot] = kt.y;
-        // the farthest diagonal neighbour inside the disk => all 8 are
-        const bool full = (float)(r2 + 4 * (abs(di) + abs(dj)) + 8) <= d2;
-        pk |= ((full ? 12 : pupil_nbr_12(gi, gj, N, d2)) << 20) | (1 << 24);
-      }
-      opk[slot] = own ? pk : -1;
+      const int gp = own ? gi * N + gj : 0;
+      const float2 kt = ktp[gp];
+      okap[slot] = kt.x;
+      ott[slot] = kt.y;
+      ogeo[slot] = geop[gp];
+      opk[slot] = own ? (li * RW + lj) | ((border ? nb_mask(gi, gj, N) : NB_ALL) << 16) : -1;
     }
   });
   if (sc[SC_FLAG] != 0.0f) {  // rejected frame: carry the state over unchanged
@@ -1079,7 +1076,10 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   __syncthreads();
   float os[SLOTS];
 #pragma unroll
-  for (int slot = 0; slot < SLOTS; ++slot) os[slot] = opk[slot] >= 0 ? sS[opk[slot] & 0xffff] : 0.f;
+  for (int slot = 0; slot < SLOTS; ++slot) {
+    opk[slot] = opk[slot] >= 0 ? opk[slot] | ((ogeo[slot] & 31) << 20) : -1;
+    os[slot] = opk[slot] >= 0 ? sS[opk[slot] & 0xffff] : 0.f;
+  }
   const float inv_sp = D.qg_inv_sp, lc = D.qg_lc, pmq = D.qg_pmq, qop = D.qg_qop;
   // ---- the four colour passes (same-colour pixels are never neighbours, so
   // each pass updates its pixels in place).  The neighbour-mask test is

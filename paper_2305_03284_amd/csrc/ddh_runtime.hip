@@ -356,7 +356,7 @@ int ddh_default_params(int N, ddh_params* p) {
 
 // Device allocation of one stream (one hipMalloc): offsets of its buffers.
 struct StreamLayout {
-  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, total;
+  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, geo, total;
   explicit StreamLayout(int N) {
     const size_t px = (size_t)N * N;
     const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
@@ -378,6 +378,7 @@ struct StreamLayout {
     desc = take(sizeof(StreamDesc));
     dptr = take(sizeof(StreamDesc*));
     diag = take(kDiagParts * 3 * sizeof(double) + 64);
+    geo = take(px);  // after the ranges cleared at creation
     total = off;
   }
 };
@@ -422,6 +423,7 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.bb = (float*)(mem + o_bb);
   h.part = (float*)(mem + o_part);
   h.scal = (float*)(mem + o_scal);
+  h.geo = (const unsigned char*)(mem + lay.geo);
   h.N = N;
   h.cur = 0;
   h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
@@ -440,6 +442,23 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.qg_lc = (float)(((double)p->qg_p - (double)p->qg_q) * std::log2(1.0 / ((double)p->qg_T * (double)p->qg_sigma)));
   h.qg_qop = p->qg_q / p->qg_p;
   h.qg_pm2 = p->qg_p - 2.0f;
+  // per-pixel pupil geometry for the M-step: the pupil-neighbour weight in
+  // twelfths and the in-pupil flag (the same integer test as the kernels')
+  std::vector<unsigned char> geo((size_t)N * N, 0);
+  {
+    const float d2 = h.pupil_d2;
+    auto inp = [&](int i, int j) {
+      const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
+      return i >= 0 && i < N && j >= 0 && j < N && (float)(di * di + dj * dj) <= d2;
+    };
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        if (!inp(i, j)) continue;
+        const int n12 = 2 * (inp(i - 1, j) + inp(i + 1, j) + inp(i, j - 1) + inp(i, j + 1)) + inp(i - 1, j - 1) +
+                        inp(i - 1, j + 1) + inp(i + 1, j - 1) + inp(i + 1, j + 1);
+        geo[(size_t)i * N + j] = (unsigned char)(n12 | 16);
+      }
+  }
   // pupil moments (exact sums over integer coordinates, in double)
   {
     double m[6] = {0, 0, 0, 0, 0, 0};
@@ -476,6 +495,8 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   };
   e = hipMemcpy(s->d, &h, sizeof(StreamDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(desc)"));
+  e = hipMemcpy(mem + lay.geo, geo.data(), geo.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(geo)"));
   StreamDesc* dv = s->d;
   e = hipMemcpy(s->dptr, &dv, sizeof(StreamDesc*), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(dptr)"));
