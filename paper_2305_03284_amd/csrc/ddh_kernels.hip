@@ -991,7 +991,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const float4* pin4 = reinterpret_cast<const float4*>(pin);
   const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
   const auto ktp = glb(D.T);
-  const unsigned char* geop = glb(D.geo);
+  const auto geop = glb(D.geo);
   float4 gr[SR], gb[SR], gph[SR];
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
