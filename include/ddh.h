@@ -80,9 +80,10 @@ typedef struct {
  * n_k 1, sigma_w2 0.1, QGGMRF (2, 1.2, 0.1, 0.2), beta_phi 0.5, r_floor 1e-8. */
 int ddh_default_params(int N, ddh_params* p);
 
-/* Create a stream: r <- 0, phi <- 0, n <- 0 (Fig. 1, first line of DDH_MBIR).
- * Allocates the per-stream device state and workspace (about 44 bytes per
- * pixel) on the current device and zeroes r and phi on hip_stream.
+/* Create a stream: r <- 0, phi <- 0, n <- 0 (Fig. 1: the loop starts from the
+ * zero state).  Allocates the per-stream device state and workspace (about 45
+ * bytes per pixel, including one byte of pupil geometry written here) on the
+ * current device and zeroes r and phi on hip_stream.
  * Errors: DDH_EINVAL (p or out NULL, parameter out of range), DDH_ENOMEM,
  * DDH_EDEVICE.  On error *out is left unchanged. */
 int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out);
