@@ -42,9 +42,9 @@ struct StreamDesc {
   float sigma2, lam, alpha, beta, r_floor;
   float qg_p, qg_q, qg_T, qg_sigma;
   // precomputed QGGMRF constants
-  float qg_inv_sp;     // 1 / sigma^p
+  float qg_inv_sp;     // 1 / sigma^p (halved when q = p, see qg_pmq)
   float qg_inv_Ts;     // 1 / (T sigma)
-  float qg_pmq;        // p - q
+  float qg_pmq;        // p - q; 1e-30 when q = p (with qg_lc = -256)
   float qg_qop;        // q / p
   float qg_pm2;        // p - 2
   float qg_lc;         // (p - q) log2(1 / (T sigma))

@@ -836,12 +836,13 @@ __device__ __forceinline__ float solve_r(float s, float A, float B) {
 // rho'(d)/d of the QGGMRF prior for p = 2:
 //   (1/sig^2) (1 + (q/2) v) / (1 + v)^2,  v = |d/(T sig)|^(2-q)
 // evaluated as u (q/2 + (1 - q/2) u) with u = 1/(1 + v) and
-// log2 v = (2-q) log2|d| + lc, lc = (2-q) log2(1/(T sig)).  (q = 2 gives
-// v = 1 for every d, the quadratic prior.)  inv_sp is folded into the
-// neighbour weights by the caller.
+// log2 v = (2-q) log2|d| + lc, lc = (2-q) log2(1/(T sig)).  q = 2 (the
+// quadratic prior, v = 1 for every d) arrives as pmq = 1e-30 and lc = -256,
+// which give v = 0 for every d, d = 0 included, with inv_sp halved.  inv_sp
+// is folded into the neighbour weights by the caller.
 __device__ __forceinline__ float qg_shape(float d, float lc, float pmq, float qop) {
   DDH_EXACT_FP
-  const float v = pmq > 0.0f ? fexp2(__builtin_fmaf(pmq, flog2(fabsf(d)), lc)) : 1.0f;
+  const float v = fexp2(__builtin_fmaf(pmq, flog2(fabsf(d)), lc));
   const float u = frcp(1.0f + v);
   return u * __builtin_fmaf(1.0f - qop, u, qop);
 }

@@ -442,6 +442,16 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.qg_lc = (float)(((double)p->qg_p - (double)p->qg_q) * std::log2(1.0 / ((double)p->qg_T * (double)p->qg_sigma)));
   h.qg_qop = p->qg_q / p->qg_p;
   h.qg_pm2 = p->qg_p - 2.0f;
+  if (!(h.qg_pmq > 0.0f)) {
+    // q = p: the edge weight does not depend on d.  The kernels evaluate
+    // v = 2^(pmq log2|d| + lc) without a branch for d = 0, so v is made 0 for
+    // every d instead of 1 (a positive pmq far too small to move lc, and lc
+    // below the exponent range): the shape is then 1 instead of 1/2, and the
+    // prior scale is halved to match (bit for bit: both are powers of two)
+    h.qg_pmq = 1e-30f;
+    h.qg_lc = -256.0f;
+    h.qg_inv_sp *= 0.5f;
+  }
   // per-pixel pupil geometry for the M-step: the pupil-neighbour weight in
   // twelfths and the in-pupil flag (the same integer test as the kernels')
   std::vector<unsigned char> geo((size_t)N * N, 0);

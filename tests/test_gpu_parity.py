@@ -349,6 +349,36 @@ def test_zero_phase_prior_weight():
     assert np.sqrt(np.mean(d * d)) < TOL_PHI
 
 
+def test_quadratic_reflectance_prior():
+    """q = p = 2 (the quadratic prior, edge weight independent of d): frames
+    from the zero state, then one EM iteration from a state whose left half is
+    constant (many neighbour differences exactly zero) against the oracle."""
+    D = _ddh()
+    torch = _torch()
+    N = 64
+    say("q = 2 frames and a flat-state EM iteration")
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=10.0, snr=10.0, speed=0.5, config_id=16))
+    prm, gp = make_pair(N, st.sigma_w2, qg_q=2.0)
+    a = O.aperture(N)
+    s = D.Stream(N, gp)
+    r_o, p_o = np.zeros((N, N)), np.zeros((N, N))
+    for n in range(3):
+        y = st.frame(n)
+        r_o, p_o = O.ddh_frame(r_o, p_o, y.astype(np.complex128), a, prm)
+        s.step(dev(y))
+        compare(f"q=2 frame {n}", *state(s), r_o, p_o, a)
+    rng = np.random.default_rng(16)
+    r0 = np.full((N, N), 0.3, dtype=np.float32)
+    r0[:, N // 2:] = rng.uniform(0.1, 1.0, (N, N - N // 2)).astype(np.float32)
+    p0 = np.where(a > 0, rng.normal(0.0, 0.3, (N, N)), 0.0).astype(np.float32)
+    s.set_state(dev(r0), dev(p0))
+    y = st.frame(3)
+    s.em(dev(y))
+    r_o, p_o = O.em(r0.astype(np.float64), p0.astype(np.float64), y.astype(np.complex128), a, prm)
+    compare("q=2 flat-state EM", *state(s), r_o, p_o, a)
+    s.close()
+
+
 def test_rejected_frame_leaves_state_unchanged():
     D = _ddh()
     torch = _torch()
