@@ -2079,22 +2079,6 @@ __device__ __forceinline__ void g_pback_a_body(const float* pin, const float* po
   kbar[p] = kb;
   tbar[p] = tb;
 }
-// part b: pupil pixels gather em of their colour-C pupil neighbours
-__device__ __forceinline__ void g_pback_b_body(const float* em, const GradPrm* Pd, float* pbar) {
-  const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  if (!in_pupil(i, j, N, P.d2)) return;
-  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
-  float acc = 0.f;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int ii = i + nb[e][0], jj = j + nb[e][1];
-    if (ii >= 0 && ii < N && jj >= 0 && jj < N) acc += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * em[g_at(ii, jj, N)];
-  }
-  pbar[p] += acc;
-}
 // data term reversed: (kbar, tbar) -> phi' (pb2 = pbar + ...), z (zbar), s2
 __global__ __launch_bounds__(256) void k_g_data_bar(const float2* yh, const float* phip, const float2* z,
                                                     const float* kap, const float* kbar, const float* tbar,
@@ -2208,33 +2192,6 @@ __device__ __forceinline__ void g_rback_a_body(const float* rin, const float* ro
   sbar[p] = sb;
   rbar[p] = own;
 }
-// part b: every pixel not of colour C gathers from its colour-C neighbours
-template <int C>
-__device__ __forceinline__ void g_rback_b_body(const float* rin, const float* Abar, const float* Bbar,
-                                                   const GradPrm* Pd, float* rbar) {
-  const GradPrm P = Pd[blockIdx.y];
-  int i, j;
-  if (!g_pix(i, j, P.N)) return;
-  const int N = P.N, p = g_at(i, j, N);
-  if ((i & 1) + 2 * (j & 1) == C) return;
-  const int nb[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
-  const float rj = rin[p];
-  float acc = 0.f;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int ii = i + nb[e][0], jj = j + nb[e][1];
-    if (!(ii >= 0 && ii < N && jj >= 0 && jj < N)) continue;
-    const int q = g_at(ii, jj, N);
-    if ((ii & 1) + 2 * (jj & 1) != C) continue;
-    const float ab = Abar[q], bb = Bbar[q];
-    if (ab == 0.0f && bb == 0.0f) continue;
-    float sh, dsh, dss;
-    g_shape(rin[q] - rj, P, sh, dsh, dss);
-    const float W = P.inv_sp * (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f);
-    acc += bb * W * sh - W * (ab + bb * rj) * dsh;
-  }
-  rbar[p] += acc;
-}
 // E-step and Eq. (3) reversed at one pixel: (mubar, sbar, r0bar) -> bbar
 // (returned), rbar of the previous state (assigned), s2 (accumulated)
 __device__ __forceinline__ float2 g_estep_bar_px(float2 bv, float2 mb, float rprev, float r, float sb, const GradPrm& P,
@@ -2340,11 +2297,51 @@ __global__ __launch_bounds__(256) void k_g_back_a(const float* pin, const float*
   g_pback_a_body<C>(pin, pout, kap, tth, Pd, pbar, em, kbar, tbar, gbeta);
   g_rback_a_body<C>(rin, rout, s, Pd, rbar, sbar, Abar, Bbar, gsr);
 }
+// Both parts b in one pass, one thread per 2 x 2 quad: each of the quad's
+// three pixels not of colour C gathers from exactly its colour-C neighbours
+// (2 vertical, 2 horizontal or 4 diagonal ones, known at compile time), in
+// neighbour order (up, down, left, right, then the diagonals).  Neighbours
+// of the other colours take no part: their em is zero in this pass and their
+// Abar, Bbar belong to other passes.
+__host__ __device__ constexpr int g_nb_di(int e) { return e == 0 || e == 4 || e == 5 ? -1 : (e == 1 || e == 6 || e == 7 ? 1 : 0); }
+__host__ __device__ constexpr int g_nb_dj(int e) { return e == 2 || e == 4 || e == 6 ? -1 : (e == 3 || e == 5 || e == 7 ? 1 : 0); }
 template <int C>
 __global__ __launch_bounds__(256) void k_g_back_b(const float* em, const float* rin, const float* Abar,
                                                   const float* Bbar, const GradPrm* Pd, float* pbar, float* rbar) {
-  g_pback_b_body(em, Pd, pbar);
-  g_rback_b_body<C>(rin, Abar, Bbar, Pd, rbar);
+  const GradPrm P = Pd[blockIdx.y];
+  int qi, qj;
+  if (!g_quad(qi, qj, P.N)) return;
+  const int N = P.N;
+  static_for<0, 4>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    if constexpr (q != C) {
+      constexpr int a = q & 1, b = q >> 1;
+      const int i = 2 * qi + a, j = 2 * qj + b, p = g_at(i, j, N);
+      const bool inp = in_pupil(i, j, N, P.d2);
+      const float rj = rin[p];
+      float accp = 0.f, accr = 0.f;
+      static_for<0, 8>([&](auto ee) {
+        constexpr int e = decltype(ee)::value;
+        constexpr int di = g_nb_di(e), dj = g_nb_dj(e);
+        if constexpr (((a + di) & 1) + 2 * ((b + dj) & 1) == C) {
+          const int ii = i + di, jj = j + dj;
+          if (ii >= 0 && ii < N && jj >= 0 && jj < N) {
+            const int qn = g_at(ii, jj, N);
+            if (inp) accp += (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f) * em[qn];
+            const float ab = Abar[qn], bb = Bbar[qn];
+            if (!(ab == 0.0f && bb == 0.0f)) {
+              float sh, dsh, dss;
+              g_shape(rin[qn] - rj, P, sh, dsh, dss);
+              const float W = P.inv_sp * (e < 4 ? 1.0f / 6.0f : 1.0f / 12.0f);
+              accr += bb * W * sh - W * (ab + bb * rj) * dsh;
+            }
+          }
+        }
+      });
+      if (inp) pbar[p] += accp;
+      rbar[p] += accr;
+    }
+  });
 }
 
 #define DDH_G_GRID(N, B) dim3(((N) * (N) + 255) / 256, (B)), dim3(256), 0, st
@@ -2414,7 +2411,7 @@ hipError_t g_launch_backward(const GradFwd& a, const GradBwd& g, const GradDev& 
   hipLaunchKernelGGL(k_g_back_a<C>, DDH_G_QGRID(N, B), C == 0 ? ps0 : a.ps[C], a.ps[C + 1], a.kap, a.tth, a.rs[C], \
                      a.rs[C + 1], a.s, d.prm, g.pbar, g.em, g.kbar, g.tbar, g.gbeta, g.rbar, g.sbar, g.Abar,      \
                      g.Bbar, g.gsr);                                                                             \
-  hipLaunchKernelGGL(k_g_back_b<C>, DDH_G_GRID(N, B), g.em, a.rs[C], g.Abar, g.Bbar, d.prm, g.pbar, g.rbar);
+  hipLaunchKernelGGL(k_g_back_b<C>, DDH_G_QGRID(N, B), g.em, a.rs[C], g.Abar, g.Bbar, d.prm, g.pbar, g.rbar);
   DDH_BK(3) DDH_BK(2) DDH_BK(1) DDH_BK(0)
 #undef DDH_BK
   hipLaunchKernelGGL(k_g_data_bar, DDH_G_GRID(N, B), a.yh, a.phip, a.z, a.kap, g.kbar, g.tbar, g.pbar, d.prm, g.pb2,
