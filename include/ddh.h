@@ -81,9 +81,11 @@ typedef struct {
 int ddh_default_params(int N, ddh_params* p);
 
 /* Create a stream: r <- 0, phi <- 0, n <- 0 (Fig. 1: the loop starts from the
- * zero state).  Allocates the per-stream device state and workspace (about 45
- * bytes per pixel, including one byte of pupil geometry written here) on the
- * current device and zeroes r and phi on hip_stream.
+ * zero state).  Allocates the per-stream device state and workspace (about 44
+ * bytes per pixel) on the current device and zeroes r and phi on hip_stream.
+ * The first stream of a given N and pupil diameter on a device also creates
+ * that shape's pupil geometry table (1 byte per pixel), which the library
+ * keeps, like its twiddle table, until the process ends. 
  * Errors: DDH_EINVAL (p or out NULL, parameter out of range), DDH_ENOMEM,
  * DDH_EDEVICE.  On error *out is left unchanged. */
 int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out);

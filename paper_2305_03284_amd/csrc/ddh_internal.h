@@ -34,7 +34,8 @@ struct StreamDesc {
   float* scal;         // SC_COUNT floats
   // per pixel: prior weight of the pupil neighbours in twelfths (bits 0-3:
   // 2 per edge and 1 per diagonal neighbour inside the pupil) and the
-  // in-pupil flag (bit 4); zero off the pupil.  Written once at creation.
+  // in-pupil flag (bit 4); zero off the pupil.  Read-only, shared by the
+  // streams of one device, N and pupil diameter.
   const unsigned char* geo;
   int N;
   int cur;             // index of the current state buffer at the start of a frame

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -82,6 +83,47 @@ int ensure_twiddles(int dev, float2** out) {
     g_tw[dev] = d;
   }
   *out = g_tw[dev];
+  return DDH_OK;
+}
+
+// The M-step's per-pixel pupil geometry: the pupil-neighbour weight in
+// twelfths (bits 0-3) and the in-pupil flag (bit 4), zero off the pupil, by
+// the kernels' own integer pupil test.  One read-only N x N byte array per
+// device and (N, pupil diameter), shared by every stream of that shape and
+// kept until the process ends (like the twiddle table).
+int ensure_geometry(int dev, int N, float d2, const unsigned char** out) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, uint32_t>, unsigned char*> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  uint32_t bits = 0;
+  memcpy(&bits, &d2, sizeof bits);
+  const auto key = std::make_tuple(dev, N, bits);
+  const auto it = cache.find(key);
+  if (it != cache.end()) {
+    *out = it->second;
+    return DDH_OK;
+  }
+  std::vector<unsigned char> geo((size_t)N * N, 0);
+  auto inp = [&](int i, int j) {
+    const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
+    return i >= 0 && i < N && j >= 0 && j < N && (float)(di * di + dj * dj) <= d2;
+  };
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (!inp(i, j)) continue;
+      const int n12 = 2 * (inp(i - 1, j) + inp(i + 1, j) + inp(i, j - 1) + inp(i, j + 1)) + inp(i - 1, j - 1) +
+                      inp(i - 1, j + 1) + inp(i + 1, j - 1) + inp(i + 1, j + 1);
+      geo[(size_t)i * N + j] = (unsigned char)(n12 | 16);
+    }
+  unsigned char* d = nullptr;
+  DDH_CHECK(hipMalloc(&d, geo.size()));
+  hipError_t e = hipMemcpy(d, geo.data(), geo.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "hipMemcpy(geometry)");
+  }
+  cache[key] = d;
+  *out = d;
   return DDH_OK;
 }
 
@@ -356,7 +398,7 @@ int ddh_default_params(int N, ddh_params* p) {
 
 // Device allocation of one stream (one hipMalloc): offsets of its buffers.
 struct StreamLayout {
-  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, geo, total;
+  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, total;
   explicit StreamLayout(int N) {
     const size_t px = (size_t)N * N;
     const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
@@ -378,7 +420,6 @@ struct StreamLayout {
     desc = take(sizeof(StreamDesc));
     dptr = take(sizeof(StreamDesc*));
     diag = take(kDiagParts * 3 * sizeof(double) + 64);
-    geo = take(px);  // after the ranges cleared at creation
     total = off;
   }
 };
@@ -400,6 +441,9 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   rc = ensure_twiddles(dev, &tw_all);
   if (rc != DDH_OK) return rc;
   const int N = p->N;
+  const unsigned char* geo = nullptr;
+  rc = ensure_geometry(dev, N, p->pupil_diameter * p->pupil_diameter, &geo);
+  if (rc != DDH_OK) return rc;
   const StreamLayout lay(N);
   const size_t o_r0 = lay.r0, o_r1 = lay.r1, o_p0 = lay.p0, o_p1 = lay.p1, o_T = lay.T, o_U = lay.U, o_bb = lay.bb;
   const size_t o_part = lay.part, o_scal = lay.scal, o_desc = lay.desc, o_dptr = lay.dptr, o_diag = lay.diag;
@@ -423,7 +467,7 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.bb = (float*)(mem + o_bb);
   h.part = (float*)(mem + o_part);
   h.scal = (float*)(mem + o_scal);
-  h.geo = (const unsigned char*)(mem + lay.geo);
+  h.geo = geo;
   h.N = N;
   h.cur = 0;
   h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
@@ -451,23 +495,6 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
     h.qg_pmq = 1e-30f;
     h.qg_lc = -256.0f;
     h.qg_inv_sp *= 0.5f;
-  }
-  // per-pixel pupil geometry for the M-step: the pupil-neighbour weight in
-  // twelfths and the in-pupil flag (the same integer test as the kernels')
-  std::vector<unsigned char> geo((size_t)N * N, 0);
-  {
-    const float d2 = h.pupil_d2;
-    auto inp = [&](int i, int j) {
-      const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
-      return i >= 0 && i < N && j >= 0 && j < N && (float)(di * di + dj * dj) <= d2;
-    };
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) {
-        if (!inp(i, j)) continue;
-        const int n12 = 2 * (inp(i - 1, j) + inp(i + 1, j) + inp(i, j - 1) + inp(i, j + 1)) + inp(i - 1, j - 1) +
-                        inp(i - 1, j + 1) + inp(i + 1, j - 1) + inp(i + 1, j + 1);
-        geo[(size_t)i * N + j] = (unsigned char)(n12 | 16);
-      }
   }
   // pupil moments (exact sums over integer coordinates, in double)
   {
@@ -505,8 +532,6 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   };
   e = hipMemcpy(s->d, &h, sizeof(StreamDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(desc)"));
-  e = hipMemcpy(mem + lay.geo, geo.data(), geo.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(geo)"));
   StreamDesc* dv = s->d;
   e = hipMemcpy(s->dptr, &dv, sizeof(StreamDesc*), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy(dptr)"));
