@@ -487,6 +487,44 @@ def test_batch_of_mixed_sizes_equals_streams_alone(graph):
     b.close()
 
 
+def test_batch_of_mixed_pupil_diameters():
+    """Streams of one N with different pupil diameters in one batch (each
+    shape has its own pupil geometry table): equal to each stream alone, and
+    the smaller pupil against the oracle."""
+    D = _ddh()
+    N = 128
+    diams = [128, 96, 128, 96]
+    sims = [synth.Stream(synth.StreamSpec(N=N, d_over_r0=8.0, snr=10.0, speed=0.5, config_id=17, stream_id=k))
+            for k in range(len(diams))]
+    pairs = [make_pair(N, sm.sigma_w2, diameter=d) for sm, d in zip(sims, diams)]
+    frames = [[dev(sm.frame(n)) for n in range(3)] for sm in sims]
+    alone = []
+    for i in range(len(diams)):
+        s = D.Stream(N, pairs[i][1])
+        for y in frames[i]:
+            s.step(y)
+        alone.append(state(s))
+        s.close()
+    streams = [D.Stream(N, pairs[i][1]) for i in range(len(diams))]
+    b = D.Batch(streams, graph=False)
+    for n in range(3):
+        say(f"mixed pupils frame {n}")
+        b.step([frames[i][n] for i in range(len(diams))])
+    for i, s in enumerate(streams):
+        r, p = state(s)
+        np.testing.assert_array_equal(r, alone[i][0])
+        np.testing.assert_array_equal(p, alone[i][1])
+    i = 1
+    a = O.aperture(N, float(diams[i]))
+    r_o, p_o = np.zeros((N, N)), np.zeros((N, N))
+    for n in range(3):
+        r_o, p_o = O.ddh_frame(r_o, p_o, sims[i].frame(n).astype(np.complex128), a, pairs[i][0])
+    compare("96-px pupil in the batch vs oracle", *alone[i], r_o, p_o, a)
+    b.close()
+    for s in streams:
+        s.close()
+
+
 def test_batch_timing_mode_matches_graph():
     D = _ddh()
     specs = _mixed_specs()[:4]
