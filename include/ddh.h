@@ -99,7 +99,10 @@ int ddh_destroy_stream(ddh_stream_t s);
  * y: device pointer, N*N complex64, read-only, must stay valid until the
  * stream reaches this step (no pointer is kept afterwards).  If the frame is
  * rejected on the device (||y - mean|| zero or non-finite) the state is left
- * unchanged and the next ddh_status() returns DDH_EDATA.  Increments n. */
+ * unchanged and the next ddh_status() returns DDH_EDATA.  Increments n.
+ * The launches are eager; a stream created while the environment variable
+ * DDH_SINGLE_GRAPH is "1" replays them as a HIP graph instead (same results,
+ * measured slower for one stream). */
 int ddh_step(ddh_stream_t s, const void* y, void* hip_stream);
 
 /* One EM iteration EM(r, phi; y) of the plain DH-MBIR loop (DH-MBIR
