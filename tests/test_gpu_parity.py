@@ -525,6 +525,38 @@ def test_batch_of_mixed_pupil_diameters():
         s.close()
 
 
+def test_batch_of_more_streams_than_one_launch_takes():
+    """72 streams of N = 64 in one batch: the frame-start launch carries at
+    most 64 streams' frame arguments, so the batch needs two of them; every
+    stream equals the same stream stepped alone (eager and graph)."""
+    D = _ddh()
+    N, S = 64, 72
+    sims = [synth.Stream(synth.StreamSpec(N=N, d_over_r0=8.0, snr=10.0, speed=0.5, config_id=18, stream_id=k))
+            for k in range(S)]
+    pairs = [make_pair(N, sm.sigma_w2) for sm in sims]
+    frames = [[dev(sm.frame(n)) for n in range(2)] for sm in sims]
+    alone = []
+    for i in range(S):
+        s = D.Stream(N, pairs[i][1])
+        for y in frames[i]:
+            s.step(y)
+        alone.append(state(s))
+        s.close()
+    for graph in (False, True):
+        say(f"{S} streams, graph={graph}")
+        streams = [D.Stream(N, pairs[i][1]) for i in range(S)]
+        b = D.Batch(streams, graph=graph)
+        for n in range(2):
+            b.step([frames[i][n] for i in range(S)])
+        for i, s in enumerate(streams):
+            r, p = state(s)
+            np.testing.assert_array_equal(r, alone[i][0])
+            np.testing.assert_array_equal(p, alone[i][1])
+        b.close()
+        for s in streams:
+            s.close()
+
+
 def test_batch_timing_mode_matches_graph():
     D = _ddh()
     specs = _mixed_specs()[:4]

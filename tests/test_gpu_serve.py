@@ -80,6 +80,30 @@ def test_server_step_mixes_match_alone():
     srv.close()
 
 
+def test_server_call_with_more_streams_than_one_launch_takes():
+    """70 streams in one server call (the frame-start launch carries at most
+    64 streams' arguments, so the call needs two), mixed N: each equals the
+    stream stepped alone."""
+    torch = _torch()
+    import paper_2305_03284_amd as D
+    sizes = [64] * 66 + [128] * 4
+    sims, frames = _setup(sizes, 2, config_id=33)
+    streams = [D.Stream(N, _params(D, N, sm.sigma_w2)) for N, sm in zip(sizes, sims)]
+    srv = D.Server(len(sizes))
+    order = list(range(len(sizes)))
+    np.random.default_rng(3).shuffle(order)
+    for n in range(2):
+        say(f"server call {n}: {len(order)} streams")
+        srv.step([streams[i] for i in order], [frames[i][n] for i in order])
+    torch.cuda.synchronize()
+    ref = _alone(D, sims, frames, [2] * len(sizes))
+    for i, s in enumerate(streams):
+        np.testing.assert_array_equal(s.reflectance().cpu().numpy(), ref[i][0])
+        np.testing.assert_array_equal(s.phase().cpu().numpy(), ref[i][1])
+        s.close()
+    srv.close()
+
+
 def test_server_rejects_bad_calls():
     torch = _torch()
     import paper_2305_03284_amd as D
