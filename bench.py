@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--cpu-frames", type=int, default=120)
     p.add_argument("--no-extras", action="store_true", help="only the timed batched step (for profiling)")
     p.add_argument("--autotune", action="store_true", help="time every tiling first and keep the fastest")
+    p.add_argument("--autotune-mix", action="store_true",
+                   help="tune the tilings of all sizes together on the whole batched step")
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     p.add_argument("--graph", action="store_true", help="replay the batched step as a HIP graph (eager launches "
                    "are the default: they measured faster)")
@@ -491,6 +493,8 @@ def main():
     px_total = sum(sp.N * sp.N for sp in specs)
 
     tiles = {}
+    if args.autotune_mix and not args.tiles:
+        D.autotune_mix([sp.N for sp in specs])
     for n_ in sorted({sp.N for sp in specs}):
         if args.tiles:
             D.set_tiles(n_, [int(v) for v in args.tiles.split(",")])

@@ -303,6 +303,19 @@ int ddh_get_tiles(int N, int* cfg);
  * column pass, 0, M-step), either may be NULL.  Synchronises the device. */
 int ddh_autotune(int N, int count, int* cfg, double* us);
 
+/* Autotune the tilings of a mix of sizes together: `count` temporary streams
+ * with sizes Ns[0..count-1] (host array, each one of 64..512) form a batch with
+ * the default lanes (one per N); the whole batched step is timed with HIP
+ * events while each distinct size's row, column and M-step tilings are varied
+ * in turn (sizes ascending), and a candidate replaces the current tiling only
+ * if the step gets more than 1 % faster.  The result is installed as with
+ * ddh_set_tiles.  cfgs (may be NULL) receives 4 ints per distinct size, sizes
+ * ascending; step_us (may be NULL) the final step time in microseconds.
+ * Synchronises the device.  Errors: DDH_EINVAL (Ns NULL, count outside
+ * 1..4096, an unsupported size), DDH_ENOMEM, DDH_EDEVICE; on error the
+ * tilings in force before the call are restored. */
+int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us);
+
 /* ------------------------------------------------------------------- misc */
 const char* ddh_error_string(int code);
 /* Last HIP error message seen by the library (static storage). */

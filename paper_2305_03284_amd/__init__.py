@@ -75,6 +75,7 @@ SIGNATURES = {
     "ddh_set_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
     "ddh_get_tiles": (_c_int, [_c_int, ctypes.POINTER(_c_int)]),
     "ddh_autotune": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)]),
+    "ddh_autotune_mix": (_c_int, [ctypes.POINTER(_c_int), _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)]),
     "ddh_error_string": (ctypes.c_char_p, [_c_int]),
     "ddh_last_error_message": (ctypes.c_char_p, []),
     "ddh_version": (ctypes.c_char_p, []),
@@ -461,5 +462,18 @@ def autotune(N: int, count: int):
     return tuple(cfg), tuple(us)
 
 
-__all__ = ["set_tiles", "get_tiles", "autotune", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_grad_batch", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+def autotune_mix(sizes):
+    """Tune the tilings of a mix of stream sizes together by timing the whole
+    batched step (ddh_autotune_mix); installs them and returns
+    ({N: cfg}, step time in microseconds)."""
+    sizes = [int(n) for n in sizes]
+    ns = (_c_int * len(sizes))(*sizes)
+    distinct = sorted(set(sizes))
+    cfgs = (_c_int * (4 * len(distinct)))()
+    us = _c_double()
+    _check(lib().ddh_autotune_mix(ns, len(sizes), cfgs, ctypes.byref(us)), "ddh_autotune_mix")
+    return {n: tuple(cfgs[4 * k:4 * k + 4]) for k, n in enumerate(distinct)}, us.value
+
+
+__all__ = ["set_tiles", "get_tiles", "autotune", "autotune_mix", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_grad_batch", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

@@ -1106,6 +1106,133 @@ int ddh_get_tiles(int N, int* cfg) {
   return DDH_OK;
 }
 
+// Tiling for a mix of sizes: the whole batched step of `count` temporary
+// streams with sizes Ns (default lanes: one per N) is timed, and each size's
+// row, column and M-step tilings are chosen in turn (coordinate descent, sizes
+// ascending), a candidate replacing the current one only when the step is
+// more than 1 % faster.  Per-kernel timing of one size alone (ddh_autotune)
+// misses how the lanes of different sizes share the device.
+int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
+  if (!Ns || count < 1 || count > 4096) return DDH_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!valid_N(Ns[i])) return DDH_EINVAL;
+  std::vector<int> sizes(Ns, Ns + count);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  const int rows_c[4] = {4, 8, 16, 32}, cols_c[4] = {4, 8, 16, 32};
+  const int ms_c[7][2] = {{16, 16}, {16, 32}, {16, 64}, {32, 32}, {32, 64}, {64, 64}, {32, 128}};
+  std::vector<ddh_stream_t> ss;
+  std::vector<const void*> ys(count);
+  float2* ybuf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::map<int, TileConfig> start;
+  for (int N : sizes) start[N] = tiles_for(N);
+  auto restore = [&](const std::map<int, TileConfig>& m) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : m) tile_cache()[kv.first] = kv.second;
+  };
+  auto cleanup = [&]() {
+    for (ddh_stream_t s : ss) ddh_destroy_stream(s);
+    if (ybuf) (void)hipFree(ybuf);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  size_t px_total = 0;
+  for (int i = 0; i < count; ++i) px_total += (size_t)Ns[i] * Ns[i];
+  hipError_t e = hipMalloc(&ybuf, sizeof(float2) * px_total);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(autotune)");
+  e = launch_synth_frames(ybuf, (long long)px_total, 54321u, nullptr);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "autotune setup");
+  }
+  int rc = DDH_OK;
+  size_t off = 0;
+  for (int i = 0; i < count && rc == DDH_OK; ++i) {
+    ddh_params p;
+    ddh_default_params(Ns[i], &p);
+    ddh_stream_t s = nullptr;
+    rc = ddh_init_stream(&p, nullptr, &s);
+    if (rc == DDH_OK) ss.push_back(s);
+    ys[i] = ybuf + off;
+    off += (size_t)Ns[i] * Ns[i];
+  }
+  // microseconds per batched step with the installed tilings: best of two
+  // runs of 10 steps after 2 warm-up steps, on a freshly created batch
+  auto time_step = [&](double* out) -> int {
+    double best = 1e30;
+    for (int rep = 0; rep < 2; ++rep) {
+      ddh_batch_t b = nullptr;
+      int r = ddh_batch_create(ss.data(), count, 0, &b);
+      if (r != DDH_OK) return r;
+      for (int f = 0; f < 2 && r == DDH_OK; ++f) r = ddh_batch_step(b, ys.data(), nullptr);
+      hipError_t he = hipEventRecord(e0, nullptr);
+      for (int f = 0; f < 10 && r == DDH_OK && he == hipSuccess; ++f) r = ddh_batch_step(b, ys.data(), nullptr);
+      if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      ddh_batch_destroy(b);
+      if (r != DDH_OK) return r;
+      if (he != hipSuccess) return hip_fail(he, "autotune timing");
+      best = std::min(best, 1e3 * (double)ms / 10.0);
+    }
+    *out = best;
+    return DDH_OK;
+  };
+  std::map<int, TileConfig> cur = start;
+  double t_best = 0.0;
+  if (rc == DDH_OK) rc = time_step(&t_best);
+  for (int N : sizes) {
+    for (int dim = 0; dim < 3 && rc == DDH_OK; ++dim) {
+      std::vector<TileConfig> cands;
+      const TileConfig c0 = cur[N];
+      if (dim == 0)
+        for (int v : rows_c) cands.push_back({v, c0.col_width, c0.m_tile_h, c0.m_tile_w});
+      else if (dim == 1)
+        for (int v : cols_c) cands.push_back({c0.row_lines, v, c0.m_tile_h, c0.m_tile_w});
+      else
+        for (const auto& m : ms_c) cands.push_back({c0.row_lines, c0.col_width, m[0], m[1]});
+      for (const TileConfig& c : cands) {
+        if (!tiles_ok(N, c) || (c.row_lines == c0.row_lines && c.col_width == c0.col_width &&
+                                c.m_tile_h == c0.m_tile_h && c.m_tile_w == c0.m_tile_w))
+          continue;
+        std::map<int, TileConfig> trial = cur;
+        trial[N] = c;
+        restore(trial);
+        double t = 0.0;
+        rc = time_step(&t);
+        if (rc != DDH_OK) break;
+        if (t < 0.99 * t_best) {
+          t_best = t;
+          cur = trial;
+        }
+      }
+      restore(cur);
+    }
+  }
+  cleanup();
+  if (rc != DDH_OK) {
+    restore(start);
+    return rc;
+  }
+  restore(cur);
+  if (cfgs) {
+    int k = 0;
+    for (int N : sizes) {
+      const TileConfig& c = cur[N];
+      cfgs[k++] = c.row_lines;
+      cfgs[k++] = c.col_width;
+      cfgs[k++] = c.m_tile_h;
+      cfgs[k++] = c.m_tile_w;
+    }
+  }
+  if (step_us) *step_us = t_best;
+  return DDH_OK;
+}
+
 int ddh_autotune(int N, int count, int* cfg, double* us) {
   if (!valid_N(N) || count < 1 || count > 4096) return DDH_EINVAL;
   const int rows_c[4] = {4, 8, 16, 32}, cols_c[4] = {4, 8, 16, 32};

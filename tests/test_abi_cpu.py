@@ -120,3 +120,11 @@ def test_mbir_and_gradient_calls_validate_before_device_work():
     same = (ddh.Params * 2)(ddh.make_params(64), ddh.make_params(64))
     half = (ctypes.c_void_p * 2)(16, None)
     assert B(same, 2, 3, ys2, ptr2, half, 2, ptr2, outs, None) == ddh.DDH_EINVAL
+
+
+def test_autotune_mix_validates_before_device_work():
+    L = ddh.lib()
+    ns = (ctypes.c_int * 3)(64, 128, 100)
+    assert L.ddh_autotune_mix(None, 3, None, None) == ddh.DDH_EINVAL
+    assert L.ddh_autotune_mix(ns, 0, None, None) == ddh.DDH_EINVAL
+    assert L.ddh_autotune_mix(ns, 3, None, None) == ddh.DDH_EINVAL  # 100 is not a supported size

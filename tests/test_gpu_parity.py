@@ -672,6 +672,21 @@ def test_autotune_installs_a_valid_tiling():
         D.set_tiles(N, (3, 8, 16, 16))
 
 
+def test_autotune_mix_installs_valid_tilings():
+    D = _ddh()
+    sizes = [64] * 4 + [128] * 2
+    before = {n: D.get_tiles(n) for n in (64, 128)}
+    cfgs, us = D.autotune_mix(sizes)
+    say(f"  autotune_mix: {cfgs} step {us:.1f} us")
+    try:
+        assert sorted(cfgs) == [64, 128] and us > 0
+        for n, c in cfgs.items():
+            assert D.get_tiles(n) == c
+    finally:
+        for n, c in before.items():
+            D.set_tiles(n, c)
+
+
 @pytest.mark.parametrize("lanes,graph", [(0, False), (0, True), (2, False), (3, True), (4, True)])
 def test_batch_lanes_equal_single_lane(lanes, graph):
     """lanes 0 is one lane per distinct N (the default), n >= 1 pixel-balanced"""
