@@ -311,9 +311,11 @@ int ddh_autotune(int N, int count, int* cfg, double* us);
  * if the step gets more than 1 % faster.  The result is installed as with
  * ddh_set_tiles.  cfgs (may be NULL) receives 4 ints per distinct size, sizes
  * ascending; step_us (may be NULL) the final step time in microseconds.
- * Synchronises the device.  Errors: DDH_EINVAL (Ns NULL, count outside
- * 1..4096, an unsupported size), DDH_ENOMEM, DDH_EDEVICE; on error the
- * tilings in force before the call are restored. */
+ * Synchronises the device.  The process-wide tilings change while the call
+ * runs: batches created meanwhile by other threads may get a candidate
+ * tiling (results do not depend on the tiling).  Errors: DDH_EINVAL (Ns
+ * NULL, count outside 1..4096, an unsupported size), DDH_ENOMEM,
+ * DDH_EDEVICE; on error the tilings in force before the call are restored. */
 int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us);
 
 /* ------------------------------------------------------------------- misc */
