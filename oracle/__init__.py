@@ -29,6 +29,14 @@ Parity status of each function (what pins it):
                                 beta, a direction in phi0)
   cost_U ...................... dense Gaussian likelihood at N=8, a=1
   strehl ...................... S=1 for constant / tilt residual, Marechal
+  phase_rms_diff, rel_l2 ...... hand-computed values on tiny grids; piston and
+                                off-pupil invariance; which argument normalises
+  noise-free recovery ......... full aperture, dark surround, known r: the
+                                true phase is a fixed point of the phase step
+                                and pulls a perturbed start back (error
+                                reduction); joint EM from a perturbed start
+                                does not recover (expected failure, recorded);
+                                the circular pupil moves the fixed point
 """
 from . import ddh, metrics  # noqa: F401
 from .ddh import Params  # noqa: F401

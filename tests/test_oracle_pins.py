@@ -511,12 +511,15 @@ def test_frames_are_seeded_and_complex64():
     assert not np.array_equal(st1.frame(4), y1)
 
 
-def test_true_phase_is_a_fixed_point_of_noise_free_phase_step():
+def test_phase_step_conventions_with_unit_wiener_weight():
     """Noise-free frame y = a exp(j phi0) F g and a signal variance far above
-    the noise (w -> 1): the E-step returns mu = b, so z = F mu = a exp(-j phi0)
-    yhat on the pupil and theta = arg(yhat conj z) = phi0; without the prior the
-    phase step must leave phi0 unchanged.  A wrong sign of the phase in A_phi,
-    A_phi^H or theta (or a conjugate missing) moves phi0 by 2 phi0 or more."""
+    the noise (w -> 1): the E-step returns mu = b, so z = F mu = a exp(-j phi)
+    yhat on the pupil and theta = arg(yhat conj z) is the phase phi used in b.
+    This pins the sign and conjugate conventions of A_phi, A_phi^H and theta (a
+    wrong sign or a missing conjugate moves theta by 2 phi or more).  It is not
+    a recovery check: with w = 1 every phase is a fixed point of the phase
+    step, so the phase is not identifiable in this limit (the recovery pins
+    below use an object with a dark surround)."""
     N = 16
     rng = np.random.default_rng(5)
     a = ddh.aperture(N)
@@ -531,12 +534,143 @@ def test_true_phase_is_a_fixed_point_of_noise_free_phase_step():
     phi1 = ddh.phi_m_step(phi0, yhat, z, a, prm)
     m = a > 0
     np.testing.assert_allclose(phi1[m], phi0[m], atol=1e-9)
-    # and from a perturbed phase the same data point back at phi0 in one step
-    # (theta does not depend on the phase used in b when w = 1: it is phi0)
+    # any other phase used in b is returned as theta too (w = 1: no information)
     phi_off = ddh.remove_tiptilt(phi0 + 0.3 * rng.standard_normal((N, N)) * m, a)
     z_off = ddh.F(ddh.e_step(np.full((N, N), 1e12), ddh.back_project(yhat, phi_off, a), 1e-9)[0])
     theta = np.angle(yhat * np.conj(z_off))
     np.testing.assert_allclose(np.angle(np.exp(1j * (theta[m] - phi_off[m]))), 0.0, atol=1e-9)
+
+
+# ------------------------------------------------- noise-free phase recovery
+#
+# A case where the reading of the E-step is exact and the phase identifiable:
+# the aperture is the whole grid (A_phi unitary, so the pointwise E-step is the
+# exact posterior), the frame is noise-free, and the object is dark outside a
+# centred disc (g = 0 there), so the Wiener weight w = r/(r + s2) is ~1 on the
+# object and ~0 around it.  The phase step is then the Fourier-magnitude /
+# object-support projection pair of phase retrieval, and the true phase is a
+# fixed point.
+
+def _support_case(N=16, seed=1, a=None, s2=1e-6, r_floor=1e-8):
+    a = np.ones((N, N)) if a is None else a
+    c = (N - 1) / 2.0
+    ii, jj = np.mgrid[0:N, 0:N]
+    support = ((ii - c) ** 2 + (jj - c) ** 2) <= (N / 4.0) ** 2
+    r = np.where(support, synth.reflectance(N, synth.rng_for(9, seed, synth.PURPOSE_REFLECTANCE)), 0.0)
+    spec = synth.kolmogorov_spectrum(2 * N, N / 6.0, synth.rng_for(9, seed, synth.PURPOSE_SCREEN))
+    ptrue = synth._remove_plane_truth(synth.screen_from_spectrum(spec)[:N, :N], a)
+    y = synth.hologram(r, ptrue, a, np.inf, synth.rng_for(9, seed, synth.PURPOSE_FRAME))
+    # the phase step's input is the field scaled to unit mean power; Normalize
+    # would also remove the mean of y, which adds mean(y) F^H(a exp(-j phi))
+    # to b, a term that is not zero around the object
+    scale2 = N * N / np.linalg.norm(y) ** 2
+    yhat = y * np.sqrt(scale2)
+    prm = ddh.Params(sigma_w2=s2, beta_phi=0.0, r_floor=r_floor)
+    r_n = np.maximum(r * scale2, r_floor)
+    pert = ddh.remove_tiptilt(
+        synth.screen_from_spectrum(synth.kolmogorov_spectrum(
+            2 * N, N / 4.0, synth.rng_for(9, seed + 100, synth.PURPOSE_SCREEN)))[:N, :N], a)
+    pert *= 0.5 / np.sqrt(np.mean(pert[a > 0] ** 2))      # 0.5 rad RMS, smooth
+    return a, yhat, r_n, ptrue, ddh.remove_tiptilt(ptrue + pert, a), prm
+
+
+def _phase_only_em(phi, yhat, r, a, prm, iters):
+    """EM iterations with r held fixed: E-step, z = F mu, phase M-step."""
+    for _ in range(iters):
+        mu, _, _ = ddh.e_step(r, ddh.back_project(yhat, phi, a), prm.sigma_w2)
+        phi = ddh.phi_m_step(phi, yhat, ddh.F(mu), a, prm)
+    return phi
+
+
+def _wrapped_rms(phi, ptrue, a):
+    """RMS over the pupil of the phase difference taken modulo 2 pi, with its
+    circular mean (piston) removed."""
+    z = np.exp(1j * (phi - ptrue))[a > 0]
+    return float(np.sqrt(np.mean(np.angle(z * np.exp(-1j * np.angle(z.sum()))) ** 2)))
+
+
+def test_true_phase_is_a_fixed_point_and_an_attractor_noise_free():
+    """Full aperture, noise-free, dark surround, reflectance known: one phase
+    step from the true phase moves it by less than 1e-6 rad, one step from a
+    0.5 rad (smooth) perturbation moves it by more than 1e-2, and 300 steps
+    bring the perturbed phase back to the truth (residual < 1e-3 rad modulo
+    2 pi, Strehl > 0.999).  Like every error-reduction phase retrieval the
+    iteration can stall at other fixed points, so over seven more objects and
+    0.3 rad starts at least six must return below 1e-2 rad.  A sign error in
+    the phase of A_phi or A_phi^H, a conjugate missing in theta, or a
+    transposed F fails this."""
+    a, yhat, r, ptrue, phi_p, prm = _support_case(seed=3)
+    m = a > 0
+    one = _phase_only_em(ptrue, yhat, r, a, prm, 1)
+    assert _wrapped_rms(one, ptrue, a) < 1e-6
+    step = _phase_only_em(phi_p, yhat, r, a, prm, 1)
+    assert np.sqrt(np.mean((step - phi_p)[m] ** 2)) > 1e-2
+    assert _wrapped_rms(phi_p, ptrue, a) > 0.45
+    back = _phase_only_em(phi_p, yhat, r, a, prm, 300)
+    assert _wrapped_rms(back, ptrue, a) < 1e-3
+    assert metrics.strehl(back, ptrue, a) > 0.999
+    converged = 0
+    for seed in range(2, 9):
+        a, yhat, r, ptrue, phi_p, prm = _support_case(seed=seed)
+        phi_p = ddh.remove_tiptilt(ptrue + 0.6 * (phi_p - ptrue), a)
+        converged += _wrapped_rms(_phase_only_em(phi_p, yhat, r, a, prm, 300), ptrue, a) < 1e-2
+    assert converged >= 6, converged
+
+
+@pytest.mark.xfail(strict=True, reason="joint EM (r re-estimated each iteration) from a perturbed phase: the r M-step "
+                   "explains the energy that the wrong phase leaks outside the object by raising r there, which "
+                   "removes the dark surround that identifies the phase; the phase then stays where it started")
+def test_joint_em_recovers_the_phase_noise_free():
+    a, yhat, r, ptrue, phi, prm = _support_case()
+    for _ in range(300):
+        r, phi = ddh.em_core(r, phi, ddh.back_project(yhat, phi, a), yhat, a, prm)
+    assert _wrapped_rms(phi, ptrue, a) < 1e-2
+
+
+def test_circular_pupil_moves_the_fixed_point_is_reported():
+    """With the circular pupil the pointwise E-step is not the exact posterior
+    (A^H A is the pupil's low-pass projection, not I): the back-projection of
+    the true field leaks outside the object, so the true phase is no longer a
+    fixed point of the phase step even in the noise-free case above.  Report
+    the size of one step from the truth (the quality gap of this reading)."""
+    N = 16
+    a, yhat, r, ptrue, _, prm = _support_case(N=N, a=ddh.aperture(N))
+    one = _phase_only_em(ptrue, yhat, r, a, prm, 1)
+    move = _wrapped_rms(one, ptrue, a)
+    print(f"circular pupil: one phase step from the true phase moves it by {move:.3f} rad RMS")
+    assert move > 1e-3
+
+
+# ---------------------------------------------------------------- metrics
+
+def test_phase_rms_diff_hand_values_and_piston_invariance():
+    """RMS over the pupil of the difference with its pupil mean removed:
+    differences (1, 2, 3) on a three-pixel pupil give sqrt(2/3); values off the
+    pupil do not count; a constant added on the pupil (piston) changes nothing;
+    the arguments commute."""
+    a = np.array([[1.0, 1.0], [1.0, 0.0]])
+    p1 = np.array([[1.5, 2.5], [3.5, 100.0]])
+    p2 = np.array([[0.5, 0.5], [0.5, -7.0]])
+    assert abs(metrics.phase_rms_diff(p1, p2, a) - math.sqrt(2.0 / 3.0)) < 1e-15
+    assert abs(metrics.phase_rms_diff(p2, p1, a) - math.sqrt(2.0 / 3.0)) < 1e-15
+    assert abs(metrics.phase_rms_diff(p1 + 4.25 * a, p2, a) - math.sqrt(2.0 / 3.0)) < 1e-14
+    assert metrics.phase_rms_diff(p1, p1 + 0.7, a) < 1e-15
+    # a pure piston difference over a real pupil is zero; a unit step on half of it is 1/2
+    N = 8
+    ap = ddh.aperture(N)
+    step = np.where(np.arange(N)[:, None] < N // 2, 1.0, 0.0) * np.ones((N, N))
+    assert abs(metrics.phase_rms_diff(step, np.zeros((N, N)), ap) - 0.5) < 1e-15
+
+
+def test_rel_l2_hand_values():
+    """||x - ref|| / ||ref||, normalised by the reference (not symmetric)."""
+    ref = np.array([[1.0, 0.0], [0.0, 0.0]])
+    x = np.array([[1.0, 2.0], [2.0, 0.0]])
+    assert abs(metrics.rel_l2(x, ref) - math.sqrt(8.0)) < 1e-15
+    assert metrics.rel_l2(ref, ref) == 0.0
+    assert abs(metrics.rel_l2(2.0 * ref, ref) - 1.0) < 1e-15
+    assert abs(metrics.rel_l2(ref, 2.0 * ref) - 0.5) < 1e-15
+    assert abs(metrics.rel_l2(np.array([3.0, 4.0]), np.array([0.0, 5.0])) - math.sqrt(10.0) / 5.0) < 1e-15
 
 
 def test_reference_gradient_against_central_differences():
