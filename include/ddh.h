@@ -49,7 +49,8 @@ typedef struct ddh_batch_s* ddh_batch_t;
  *   pupil_diameter  circular aperture a (diagonal of D_a) of this diameter in
  *                   pixels, centred at ((N-1)/2, (N-1)/2): pixel (i, j) is in
  *                   the pupil iff (2i-N+1)^2 + (2j-N+1)^2 <= diameter^2.
- *                   0 < diameter <= N*sqrt(2).
+ *                   0 < diameter <= N*sqrt(2).  Used when ddh_init_stream
+ *                   gets no aperture array.
  *   lambda, alpha   weights of Eq. (3), each in [0, 1] (paper: 0.45, 0.025).
  *   n_k             EM iterations per frame, >= 1 (Fig. 1; paper: 1).
  *   sigma_w2        noise variance of the normalised data, > 0.
@@ -81,14 +82,28 @@ typedef struct {
 int ddh_default_params(int N, ddh_params* p);
 
 /* Create a stream: r <- 0, phi <- 0, n <- 0 (Fig. 1: the loop starts from the
- * zero state).  Allocates the per-stream device state and workspace (about 44
- * bytes per pixel) on the current device and zeroes r and phi on hip_stream.
- * The first stream of a given N and pupil diameter on a device also creates
- * that shape's pupil geometry table (1 byte per pixel), which the library
- * keeps, like its twiddle table, until the process ends. 
- * Errors: DDH_EINVAL (p or out NULL, parameter out of range), DDH_ENOMEM,
- * DDH_EDEVICE.  On error *out is left unchanged. */
-int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out);
+ * zero state).
+ *   aperture  the camera aperture a, the diagonal of D_a in the operator
+ *             A_phi = D_a D(exp(j phi)) F Gamma (Forward Model section): N*N
+ *             floats, row-major, in host or device memory, each 0 or 1
+ *             (binary: a pixel is measured or not); read during the call
+ *             only.  RemoveTipTilt, Normalize's consumers, the phase update
+ *             (which runs on aperture pixels only, with prior neighbours in
+ *             the aperture) and the diagnostics all use it.  NULL: the circle
+ *             of p->pupil_diameter described above (p->pupil_diameter is
+ *             ignored when an array is given).
+ * Allocates the per-stream device state and workspace (about 45 bytes per
+ * pixel; ddh_stream_bytes) on the current device and zeroes r and phi on
+ * hip_stream.  The first stream of a given N and pupil diameter on a device
+ * also creates that circle's aperture table (1 byte per pixel), which the
+ * library keeps, like its twiddle table, until the process ends; a stream
+ * given an array keeps its own table.
+ * Errors: DDH_EINVAL (p or out NULL, parameter out of range, an aperture
+ * value other than 0 or 1, an aperture with no pixel, or one whose pixels
+ * all lie on one line so that the plane of RemoveTipTilt is not determined;
+ * these checks happen before any device work), DDH_ENOMEM, DDH_EDEVICE.  On
+ * error *out is left unchanged. */
+int ddh_init_stream(const ddh_params* p, const float* aperture, void* hip_stream, ddh_stream_t* out);
 
 /* Release a stream and its device memory.  Synchronises the device first.
  * Destroying NULL is DDH_EINVAL.  The handle must not be used afterwards. */
@@ -226,6 +241,24 @@ int ddh_server_destroy(ddh_server_t s);
  * returns.  DDH_EINVAL for a repeated stream or a null frame. */
 int ddh_server_step(ddh_server_t s, const ddh_stream_t* streams, const void* const* y, int count,
                     void* hip_stream);
+
+/* One DDH frame on each of `count` distinct streams (any mix of N and n_k),
+ * without a batch or server handle: the one-shot form of ReadData /
+ * WriteData of Fig. 1 for many streams.  streams: host array of handles; y:
+ * host array of device pointers to their frames (N*N complex64 each); both
+ * may be reused once the call returns; each frame must stay valid until
+ * hip_stream reaches the step.  Per-stream numerics are those of ddh_step:
+ * each stream's result is bit-identical to stepping it alone.  The frames of
+ * each N run on an internal HIP stream forked from and joined back into
+ * hip_stream, so that different sizes overlap.  The first call on a given
+ * (device, hip_stream) pair allocates a device list of descriptor pointers
+ * (8 bytes per stream, at least 64) and four internal HIP streams, kept until
+ * the process ends; a later call on that pair with more streams than the
+ * list holds synchronises hip_stream and replaces it.  Calls on one HIP
+ * stream must come from one host thread at a time.  All streams must be on
+ * one device (DDH_ESTATE otherwise).  DDH_EINVAL for a NULL array with
+ * count > 0, a repeated stream, a NULL frame or count > 2^20. */
+int ddh_step_batch(const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream);
 
 /* -------------------------------------------------------- differentiation */
 

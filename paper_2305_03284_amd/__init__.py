@@ -42,7 +42,7 @@ class GradOut(ctypes.Structure):
 
 SIGNATURES = {
     "ddh_default_params": (_c_int, [_c_int, ctypes.POINTER(Params)]),
-    "ddh_init_stream": (_c_int, [ctypes.POINTER(Params), _c_void_p, ctypes.POINTER(_c_void_p)]),
+    "ddh_init_stream": (_c_int, [ctypes.POINTER(Params), _c_void_p, _c_void_p, ctypes.POINTER(_c_void_p)]),
     "ddh_destroy_stream": (_c_int, [_c_void_p]),
     "ddh_step": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
     "ddh_em": (_c_int, [_c_void_p, _c_void_p, _c_void_p]),
@@ -66,6 +66,7 @@ SIGNATURES = {
     "ddh_server_destroy": (_c_int, [_c_void_p]),
     "ddh_server_step": (_c_int, [_c_void_p, ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int,
                                  _c_void_p]),
+    "ddh_step_batch": (_c_int, [ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int, _c_void_p]),
     "ddh_unrolled_grad": (_c_int, [ctypes.POINTER(Params), _c_int, ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p,
                                    _c_int, _c_void_p, ctypes.POINTER(GradOut), _c_void_p]),
     "ddh_unrolled_grad_batch": (_c_int, [ctypes.POINTER(Params), _c_int, _c_int, ctypes.POINTER(_c_void_p),
@@ -153,14 +154,40 @@ def _check_frame(y, N):
         raise ValueError(f"frame must be a contiguous complex64 CUDA tensor of shape ({N}, {N})")
 
 
-class Stream:
-    """One DDH-MBIR stream with device-resident state (r, phi, n)."""
+def _aperture_ptr(aperture, N):
+    """(pointer, keep-alive object) of an N x N float32 aperture given as a
+    numpy array (host) or a torch tensor (host or CUDA); (None, None) for the
+    circle of the parameters' diameter."""
+    if aperture is None:
+        return None, None
+    torch = _torch()
+    if isinstance(aperture, torch.Tensor):
+        a = aperture.detach().to(torch.float32).contiguous()
+        if tuple(a.shape) != (N, N):
+            raise ValueError(f"aperture must have shape ({N}, {N})")
+        return ctypes.c_void_p(a.data_ptr()), a
+    import numpy as np
+    a = np.ascontiguousarray(aperture, dtype=np.float32)
+    if a.shape != (N, N):
+        raise ValueError(f"aperture must have shape ({N}, {N})")
+    return ctypes.c_void_p(a.ctypes.data), a
 
-    def __init__(self, N: int, params: Params | None = None, **kw):
+
+class Stream:
+    """One DDH-MBIR stream with device-resident state (r, phi, n).
+    ``aperture``: optional N x N binary array (numpy or torch, host or CUDA),
+    the diagonal of D_a; default the circle of ``pupil_diameter``."""
+
+    def __init__(self, N: int, params: Params | None = None, aperture=None, **kw):
         self.N = N
         self.params = params if params is not None else make_params(N, **kw)
         h = ctypes.c_void_p()
-        _check(lib().ddh_init_stream(ctypes.byref(self.params), _stream_ptr(), ctypes.byref(h)), "ddh_init_stream")
+        ap, keep = _aperture_ptr(aperture, N)
+        if keep is not None and hasattr(keep, "is_cuda") and keep.is_cuda:
+            _torch().cuda.current_stream().synchronize()  # the library reads the array synchronously
+        _check(lib().ddh_init_stream(ctypes.byref(self.params), ap, _stream_ptr(), ctypes.byref(h)),
+               "ddh_init_stream")
+        del keep
         self._h = h
 
     @property
@@ -294,6 +321,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def step_batch(streams, ys) -> None:
+    """One frame on each of several distinct streams (any mix of N), without a
+    handle (ddh_step_batch), on the current torch stream."""
+    if len(ys) != len(streams):
+        raise ValueError("one frame per stream")
+    for y, s in zip(ys, streams):
+        _check_frame(y, s.N)
+    n = len(streams)
+    hs = (ctypes.c_void_p * max(n, 1))(*[s.handle.value for s in streams])
+    ps = (ctypes.c_void_p * max(n, 1))(*[y.data_ptr() for y in ys])
+    _check(lib().ddh_step_batch(hs, ps, n, _stream_ptr()), "ddh_step_batch")
 
 
 def stream_bytes(N: int) -> int:
@@ -475,5 +515,5 @@ def autotune_mix(sizes):
     return {n: tuple(cfgs[4 * k:4 * k + 4]) for k, n in enumerate(distinct)}, us.value
 
 
-__all__ = ["set_tiles", "get_tiles", "autotune", "autotune_mix", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_grad_batch", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
+__all__ = ["step_batch", "set_tiles", "get_tiles", "autotune", "autotune_mix", "Stream", "Batch", "Server", "stream_bytes", "unrolled_grad", "unrolled_grad_batch", "unrolled_loss_fn", "GradOut", "Params", "make_params", "default_params", "fft2", "lib", "DDHError",
            "SIGNATURES", "LIB_PATH"]

@@ -32,14 +32,14 @@ struct StreamDesc {
   float* bb;           // |b|^2 from the column pass
   float* part;         // stats partials, PART_STRIDE floats per stats block
   float* scal;         // SC_COUNT floats
-  // per pixel: prior weight of the pupil neighbours in twelfths (bits 0-3:
-  // 2 per edge and 1 per diagonal neighbour inside the pupil) and the
-  // in-pupil flag (bit 4); zero off the pupil.  Read-only, shared by the
-  // streams of one device, N and pupil diameter.
+  // the aperture a (D_a), one byte per pixel: prior weight of the aperture
+  // neighbours in twelfths (bits 0-3: 2 per edge and 1 per diagonal
+  // neighbour inside the aperture) and the in-aperture flag (bit 4); zero
+  // off the aperture.  Read-only: for a circular pupil shared by the streams
+  // of one device, N and diameter; for an aperture array the stream's own.
   const unsigned char* geo;
   int N;
   int cur;             // index of the current state buffer at the start of a frame
-  float pupil_d2;      // diameter^2 (pixel (i,j) in pupil iff (2i-N+1)^2+(2j-N+1)^2 <= d2)
   float sigma2, lam, alpha, beta, r_floor;
   float qg_p, qg_q, qg_T, qg_sigma;
   // precomputed QGGMRF constants
@@ -115,7 +115,7 @@ hipError_t launch_max_abs2(const float2* x, int n, double* partials, int nparts,
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t st);
 hipError_t launch_synth_frames(float2* y, long long n, unsigned int seed, hipStream_t st);
 hipError_t launch_copy(float* dst, const float* src, long long n, hipStream_t st);
-hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st);
+hipError_t launch_copy_pupil(float* dst, const float* src, int N, const unsigned char* geo, hipStream_t st);
 
 // --- unrolled frames with a hand-written adjoint (ddh_kernels.hip) ---------
 // one stream's constants (a device array of these, one per stream of a batch)

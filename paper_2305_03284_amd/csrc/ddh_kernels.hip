@@ -284,6 +284,13 @@ __device__ __forceinline__ bool in_pupil(int i, int j, int N, float d2) {
   return (float)(__mul24(di, di) + __mul24(dj, dj)) <= d2;
 }
 
+// Per-pixel aperture geometry byte of a stream (D_a of the Forward Model):
+// bit 4 = the pixel is in the aperture, bits 0-3 = prior weight of its
+// aperture neighbours in twelfths (2 per edge, 1 per diagonal neighbour);
+// zero off the aperture.  Built on the host from the circle or the mask.
+constexpr unsigned GEO_IN = 16u;
+__device__ __forceinline__ bool geo_in(unsigned g) { return (g & GEO_IN) != 0u; }
+
 // least-squares plane c0 + c1 (i - c) + c2 (j - c), c = (N-1)/2 (RemoveTipTilt)
 __device__ __forceinline__ float plane_val(float c0, float c1, float c2, int i, int j, int N) {
   DDH_EXACT_FP
@@ -398,21 +405,21 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
   // descriptor fields are read once, here: read inside the loops they would
   // be re-read after every store (which may alias the descriptor) and each
   // re-read waits for every memory operation in flight
-  const float d2 = D.pupil_d2;
+  const auto geo = glb(D.geo);
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + threadIdx.x];
   // phi is loaded at every pixel (branch-free: a load under a per-pixel
   // branch makes the compiler wait for all loads in flight at each join) and
-  // masked to the pupil afterwards
+  // masked to the pupil afterwards with the aperture bytes
   if (with_phi) {
+    unsigned gg[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) ph[k] = phi[base + k * 256 + threadIdx.x];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int idx = base + k * 256 + threadIdx.x;
-      ph[k] = in_pupil(idx / N, idx % N, N, d2) ? ph[k] : 0.0f;
-    }
+    for (int k = 0; k < 16; ++k) gg[k] = geo[base + k * 256 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ph[k] = geo_in(gg[k]) ? ph[k] : 0.0f;
   } else {
 #pragma unroll
     for (int k = 0; k < 16; ++k) ph[k] = 0.0f;
@@ -546,16 +553,18 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   const int row = xb.item * LPW + line;
   const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
   const float2* y = glb(D.y) + row * N;
-  const float d2 = D.pupil_d2;  // read before any store (see k_stats)
-  // global reads first (they depend on nothing computed here): the row of y
-  // and phi, and the twiddle table into LDS
+  const auto geo = glb(D.geo) + row * N;  // read before any store (see k_stats)
+  // global reads first (they depend on nothing computed here): the row of y,
+  // phi and the aperture bytes, and the twiddle table into LDS
   float2 yv[E];
   float phv[E];
+  unsigned gv[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
     yv[i] = y[n];
     phv[i] = phi[n];
+    gv[i] = geo[n];
   }
   for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
   float sc[SC_COUNT];
@@ -579,7 +588,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
-    if (in_pupil(row, n, N, d2)) {
+    if (geo_in(gv[i])) {
       const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, n, N) : phv[i];
       float sn, cs;
       fsincos(p, &sn, &cs);
@@ -699,14 +708,18 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
   const float2* y = glb(D.y) + row * N;
   // descriptor fields are read before any store (see k_stats)
-  const float d2 = D.pupil_d2;
+  const auto geo = glb(D.geo) + row * N;
   const float c2s = 2.0f / D.sigma2;
   float2* out = glb(D.T) + row * N;
   float* pmat = glb(D.phi[((D.cur + k) & 1) ^ 1]) + row * N;
-  // every global read is issued up front: the row, and y and phi at this
-  // thread's output positions that lie in the pupil
+  // every global read is issued up front: the aperture bytes at this
+  // thread's output positions (first: the loads below wait for them), the
+  // row, and y and phi at the output positions that lie in the pupil
   float2 yv[E];
   float phv[E];
+  unsigned gv[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) gv[i] = geo[last_pos<N, -1>(i, t)];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = u[first_pos<N, -1>(i, t)];
 #pragma unroll
@@ -714,7 +727,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
     const int m = last_pos<N, -1>(i, t);
     yv[i] = make_float2(0.f, 0.f);
     phv[i] = 0.f;
-    if (in_pupil(row, m, N, d2)) {
+    if (geo_in(gv[i])) {
       yv[i] = y[m];
       phv[i] = phi[m];
     }
@@ -730,7 +743,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
   for (int i = 0; i < E; ++i) {
     const int m = last_pos<N, -1>(i, t);
     float2 res = make_float2(0.f, 0.f);
-    if (in_pupil(row, m, N, d2)) {
+    if (geo_in(gv[i])) {
       const float2 z = cscale(v[i], invN);
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
       const float p = use_plane ? phv[i] - plane_val(c0, c1, c2, row, m, N) : phv[i];
@@ -979,7 +992,6 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   float* rout = glb(D.r[in ^ 1]);
   float* pout = glb(D.phi[in ^ 1]);
   const float* sc = glb(D.scal);
-  const float d2 = D.pupil_d2;
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
   // ---- every global read is issued up front: r, |b|^2 and phi of the
   // region in 4-pixel vectors (the halo is 4 wide and tile origins are
@@ -993,17 +1005,21 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
   const auto ktp = glb(D.T);
   const auto geop = glb(D.geo);
+  const auto geo4 = reinterpret_cast<gptr<const unsigned>>(geop);
   float4 gr[SR], gb[SR], gph[SR];
+  unsigned gw[SR];  // aperture bytes of the 4 pixels of the vector
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
     const int idx = threadIdx.x + q * BT;
     const int li = idx / RW4, gi = gi0 + li, gj = gj0 + 4 * (idx - li * RW4);
     gr[q] = gb[q] = gph[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    gw[q] = 0u;
     if (idx < RP4 && gi >= 0 && gi < N && gj >= 0 && gj < N) {
       const int v = (gi * N + gj) / 4;
       gr[q] = rin4[v];
       gb[q] = bb4[v];
       gph[q] = pin4[v];
+      gw[q] = geo4[v];
     }
   }
   // per own pixel, one packed word: LDS offset (bits 0-15), neighbour mask
@@ -1058,14 +1074,11 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
         const float rv[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
         const float bv[4] = {gb[q].x, gb[q].y, gb[q].z, gb[q].w};
         const float pv[4] = {gph[q].x, gph[q].y, gph[q].z, gph[q].w};
-        const int di = 2 * gi - N + 1;
-        const int di2 = __mul24(di, di);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           r[e] = do_rinit ? rinit_of(rv[e], bv[e], lam, alpha, fl) : rv[e];
           sv[e] = second_moment(wiener_of(r[e], s2), bv[e], s2);
-          const int dj = 2 * (gj + e) - N + 1;
-          if ((float)(di2 + __mul24(dj, dj)) <= d2) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
+          if (geo_in(gw[q] >> (8 * e))) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
         }
       }
       const int o4 = li * RW4 + c4;
@@ -1158,9 +1171,8 @@ __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) 
   rq[5] = (up && rt) ? rw[p - N + 1] : 0.f;
   rq[6] = (dn && lf) ? rw[p + N - 1] : 0.f;
   rq[7] = (dn && rt) ? rw[p + N + 1] : 0.f;
-  const float d2 = D.pupil_d2;
-  const int di = 2 * gi - N + 1, dj = 2 * gj - N + 1;
-  const bool pup = (float)(di * di + dj * dj) <= d2;
+  const unsigned gp = glb(D.geo)[p];
+  const bool pup = geo_in(gp);
   float pq[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float2 kt = make_float2(0.f, 0.f);
   if (pup) {
@@ -1186,8 +1198,7 @@ __global__ __launch_bounds__(256) void k_mpass(StreamDesc* const* dptrs, int k) 
   rw[p] = r_pixel<true>(rp, s, rq, nb_mask(gi, gj, N), D.qg_inv_sp, D.qg_lc, D.qg_pmq, D.qg_qop, D.r_floor);
   // ---- phi update
   if (pup) {
-    const float P = pupil_weight_of(pupil_nbr_12(gi, gj, N, d2));
-    pw[p] = phi_pixel(pq, P, kt.x, kt.y, 2.0f * D.beta, pw[p]);
+    pw[p] = phi_pixel(pq, pupil_weight_of((int)(gp & 15u)), kt.x, kt.y, 2.0f * D.beta, pw[p]);
   }
 }
 
@@ -1277,13 +1288,13 @@ __global__ __launch_bounds__(256) void k_cost_terms(const StreamDesc* dp, int pa
     acc[0] += (bx * bx + by * by) / (ri + s2) + log(ri + s2);
     const int offs[4][2] = {{0, 1}, {1, 0}, {1, 1}, {1, -1}};
     const double bw[4] = {1.0 / 6.0, 1.0 / 6.0, 1.0 / 12.0, 1.0 / 12.0};
-    const bool pi_ = in_pupil(i, j, N, D.pupil_d2);
+    const bool pi_ = geo_in(glb(D.geo)[idx]);
     for (int q = 0; q < 4; ++q) {
       const int ii = i + offs[q][0], jj = j + offs[q][1];
       if (ii < 0 || ii >= N || jj < 0 || jj >= N) continue;
       const int o = ii * N + jj;
       acc[0] += bw[q] * qg_rho_d(ri - (double)r[o], D);
-      if (pi_ && in_pupil(ii, jj, N, D.pupil_d2)) {
+      if (pi_ && geo_in(glb(D.geo)[o])) {
         const double dph = (double)phi[idx] - (double)phi[o];
         acc[0] += (double)D.beta * bw[q] * dph * dph;
       }
@@ -1304,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_strehl_sums(const StreamDesc* dp, int p
   double acc[3] = {0, 0, 0};
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
     const int i = idx / N, j = idx - i * N;
-    if (!in_pupil(i, j, N, D.pupil_d2)) continue;
+    if (!geo_in(glb(D.geo)[idx])) continue;
     const double psi = (double)phi[idx] - (double)phi_true[idx];
     acc[0] += psi;
     acc[1] += (i - c) * psi;
@@ -1328,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_strehl_field(const StreamDesc* dp, int 
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N; idx += gridDim.x * blockDim.x) {
     const int i = idx / N, j = idx - i * N;
     float2 f = make_float2(0.f, 0.f);
-    if (in_pupil(i, j, N, D.pupil_d2)) {
+    if (geo_in(glb(D.geo)[idx])) {
       if (phi_true) {
         const double psi = (double)phi[idx] - (double)phi_true[idx] - (coef[0] + coef[1] * (i - c) + coef[2] * (j - c));
         double sn, cs;
@@ -1383,7 +1394,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1_cur(const StreamD
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int n = first_pos<N, +1>(i, t);
-    if (in_pupil(row, n, N, D.pupil_d2)) {
+    if (geo_in(glb(D.geo)[row * N + n])) {
       float sn, cs;
       sincosf(phi[n], &sn, &cs);
       const float2 yv = y[n];
@@ -1425,12 +1436,12 @@ __global__ void k_fill_zero(float* p, long long n) {
     p[i] = 0.0f;
 }
 // phi with the off-pupil values set to zero (the state invariant)
-__global__ void k_copy_pupil(float* dst, const float* src, int N, float d2) {
+__global__ void k_copy_pupil(float* dst, const float* src, int N, const unsigned char* geo) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x)
-    dst[i] = in_pupil(i / N, i % N, N, d2) ? src[i] : 0.0f;
+    dst[i] = geo_in(geo[i]) ? src[i] : 0.0f;
 }
-hipError_t launch_copy_pupil(float* dst, const float* src, int N, float d2, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_pupil, dim3((N * N + 255) / 256), dim3(256), 0, st, dst, src, N, d2);
+hipError_t launch_copy_pupil(float* dst, const float* src, int N, const unsigned char* geo, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_pupil, dim3((N * N + 255) / 256), dim3(256), 0, st, dst, src, N, geo);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <unordered_set>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -20,13 +21,28 @@ using namespace ddh;
 
 namespace {
 
-constexpr uint32_t kAlive = 0xDD4B1A5Eu;
-constexpr uint32_t kDead = 0xDEADDEADu;
 constexpr int kMaxDev = 64;
 constexpr int kDiagParts = 256;
 
 thread_local std::string g_last_err;
 std::mutex g_mu;
+
+// Handles currently alive (streams, batches, servers): a handle is checked by
+// membership here, never by reading through a pointer that may be freed.
+std::mutex g_live_mu;
+std::unordered_set<const void*> g_live;
+void live_add(const void* h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.insert(h);
+}
+void live_remove(const void* h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.erase(h);
+}
+bool is_live(const void* h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return g_live.count(h) != 0;
+}
 float2* g_tw[kMaxDev] = {nullptr};
 
 int hip_fail(hipError_t e, const char* what) {
@@ -46,11 +62,15 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool valid_N(int N) { return N == 64 || N == 128 || N == 256 || N == 512; }
 
-int validate(const ddh_params* p) {
+// check_diameter: the aperture is the circle of p->pupil_diameter (no
+// aperture array given)
+int validate(const ddh_params* p, bool check_diameter = true) {
   if (!p) return DDH_EINVAL;
   if (!valid_N(p->N)) return DDH_EINVAL;
   auto fin = [](float x) { return std::isfinite(x); };
-  if (!fin(p->pupil_diameter) || !(p->pupil_diameter > 0.f) || p->pupil_diameter > p->N * 1.41421357f) return DDH_EINVAL;
+  if (check_diameter &&
+      (!fin(p->pupil_diameter) || !(p->pupil_diameter > 0.f) || p->pupil_diameter > p->N * 1.41421357f))
+    return DDH_EINVAL;
   if (!fin(p->lambda) || p->lambda < 0.f || p->lambda > 1.f) return DDH_EINVAL;
   if (!fin(p->alpha) || p->alpha < 0.f || p->alpha > 1.f) return DDH_EINVAL;
   if (p->n_k < 1 || p->n_k > 1024) return DDH_EINVAL;
@@ -86,9 +106,36 @@ int ensure_twiddles(int dev, float2** out) {
   return DDH_OK;
 }
 
-// The M-step's per-pixel pupil geometry: the pupil-neighbour weight in
-// twelfths (bits 0-3) and the in-pupil flag (bit 4), zero off the pupil, by
-// the kernels' own integer pupil test.  One read-only N x N byte array per
+// Per-pixel aperture bytes from the binary aperture inside[] (N*N, 0 or 1):
+// the aperture-neighbour weight in twelfths (bits 0-3: 2 per edge and 1 per
+// diagonal neighbour in the aperture) and the in-aperture flag (bit 4), zero
+// off the aperture.  Every kernel reads the aperture through these bytes.
+std::vector<unsigned char> geometry_bytes(int N, const std::vector<unsigned char>& inside) {
+  std::vector<unsigned char> geo((size_t)N * N, 0);
+  auto inp = [&](int i, int j) { return i >= 0 && i < N && j >= 0 && j < N && inside[(size_t)i * N + j] != 0; };
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (!inp(i, j)) continue;
+      const int n12 = 2 * (inp(i - 1, j) + inp(i + 1, j) + inp(i, j - 1) + inp(i, j + 1)) + inp(i - 1, j - 1) +
+                      inp(i - 1, j + 1) + inp(i + 1, j - 1) + inp(i + 1, j + 1);
+      geo[(size_t)i * N + j] = (unsigned char)(n12 | 16);
+    }
+  return geo;
+}
+
+// The circular pupil of diameter^2 d2 centred at ((N-1)/2, (N-1)/2): pixel
+// (i, j) is inside iff (2i-N+1)^2 + (2j-N+1)^2 <= d2 (integer arithmetic).
+std::vector<unsigned char> circle_mask(int N, float d2) {
+  std::vector<unsigned char> m((size_t)N * N, 0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
+      m[(size_t)i * N + j] = (float)(di * di + dj * dj) <= d2 ? 1 : 0;
+    }
+  return m;
+}
+
+// Aperture bytes of a circular pupil: one read-only N x N byte array per
 // device and (N, pupil diameter), shared by every stream of that shape and
 // kept until the process ends (like the twiddle table).
 int ensure_geometry(int dev, int N, float d2, const unsigned char** out) {
@@ -103,18 +150,7 @@ int ensure_geometry(int dev, int N, float d2, const unsigned char** out) {
     *out = it->second;
     return DDH_OK;
   }
-  std::vector<unsigned char> geo((size_t)N * N, 0);
-  auto inp = [&](int i, int j) {
-    const int di = 2 * i - N + 1, dj = 2 * j - N + 1;
-    return i >= 0 && i < N && j >= 0 && j < N && (float)(di * di + dj * dj) <= d2;
-  };
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      if (!inp(i, j)) continue;
-      const int n12 = 2 * (inp(i - 1, j) + inp(i + 1, j) + inp(i, j - 1) + inp(i, j + 1)) + inp(i - 1, j - 1) +
-                      inp(i - 1, j + 1) + inp(i + 1, j - 1) + inp(i + 1, j + 1);
-      geo[(size_t)i * N + j] = (unsigned char)(n12 | 16);
-    }
+  const std::vector<unsigned char> geo = geometry_bytes(N, circle_mask(N, d2));
   unsigned char* d = nullptr;
   DDH_CHECK(hipMalloc(&d, geo.size()));
   hipError_t e = hipMemcpy(d, geo.data(), geo.size(), hipMemcpyHostToDevice);
@@ -177,7 +213,6 @@ int twiddle_offset(int N) {
 
 // ------------------------------------------------------------------ stream
 struct ddh_stream_s {
-  uint32_t magic = kAlive;
   ddh_params prm{};
   int N = 0;
   int device = 0;
@@ -192,7 +227,6 @@ struct ddh_stream_s {
   hipStream_t cap = nullptr;     // internal stream for graph capture
   hipGraphExec_t gexec = nullptr;
   bool use_graph = false;
-  bool alive() const { return magic == kAlive; }
 };
 
 // ------------------------------------------------------------------ batch
@@ -214,7 +248,6 @@ struct Lane {
 };
 
 struct ddh_batch_s {
-  uint32_t magic = kAlive;
   std::vector<ddh_stream_t> streams;  // input order
   std::vector<int> pos;               // grouped position of input stream i
   std::vector<Group> groups;          // all groups (every lane), for timing mode
@@ -241,13 +274,11 @@ struct ddh_batch_s {
   size_t pool_used = 0;
   double acc_ms[KK_COUNT] = {0};
   long long acc_n[KK_COUNT] = {0};
-  bool alive() const { return magic == kAlive; }
 };
 
 // Continuous-batching server: a device list of descriptor pointers, filled per
 // call by the stats kernel from its arguments.
 struct ddh_server_s {
-  uint32_t magic = kAlive;
   int device = 0;
   int max = 0;
   StreamDesc** list = nullptr;  // device, max entries
@@ -261,7 +292,6 @@ struct ddh_server_s {
   // back into the caller's stream
   hipStream_t lane[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool alive() const { return magic == kAlive; }
 };
 
 namespace {
@@ -269,6 +299,41 @@ namespace {
 // Enqueue one frame (mode 1: DDH frame with prologue; mode 0: plain EM) for
 // the streams in `dptrs` (grouped by N).  `ev` (optional) records events
 // around every launch.
+// The EM iterations of one frame (everything after the stats launch) for
+// `ngroups` groups of streams whose descriptor pointers sit at
+// dptrs[g.off, g.off + g.count).
+template <class OnLaunch>
+int enqueue_iters(StreamDesc** dptrs, const Group* groups, int ngroups, int n_k, int mode, hipStream_t st,
+                  OnLaunch&& around) {
+  hipError_t e;
+  const int iters = mode ? n_k : 1;
+  for (int k = 0; k < iters; ++k) {
+    const int first = (mode && k == 0) ? 1 : 0;
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      e = around(KK_ROW1,
+                 [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, k == 0, mode, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_row1");
+    }
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      e = around(KK_COL, [&] { return launch_col(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_col");
+    }
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      e = around(KK_ROW2, [&] { return launch_row2(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_row2");
+    }
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      e = around(KK_MSTEP, [&] { return launch_mstep(dptrs + g.off, g.count, g.N, k, first, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_mstep");
+    }
+  }
+  return DDH_OK;
+}
+
 template <class OnLaunch>
 int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int total, int n_k, int mode,
                   hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr,
@@ -281,29 +346,8 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
     });
     if (e != hipSuccess) return hip_fail(e, "launch_stats");
   }
-  const int iters = mode ? n_k : 1;
-  for (int k = 0; k < iters; ++k) {
-    const int first = (mode && k == 0) ? 1 : 0;
-    for (const Group& g : groups) {
-      e = around(KK_ROW1,
-                 [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, k == 0, mode, g.tc, st); });
-      if (e != hipSuccess) return hip_fail(e, "launch_row1");
-    }
-    for (const Group& g : groups) {
-      e = around(KK_COL, [&] { return launch_col(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
-      if (e != hipSuccess) return hip_fail(e, "launch_col");
-    }
-    for (const Group& g : groups) {
-      e = around(KK_ROW2, [&] { return launch_row2(dptrs + g.off, g.count, g.N, g.tw, k, first, g.tc, st); });
-      if (e != hipSuccess) return hip_fail(e, "launch_row2");
-    }
-    for (const Group& g : groups) {
-      e = around(KK_MSTEP, [&] { return launch_mstep(dptrs + g.off, g.count, g.N, k, first, first, g.tc, st); });
-      if (e != hipSuccess) return hip_fail(e, "launch_mstep");
-    }
-  }
   (void)total;
-  return DDH_OK;
+  return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around);
 }
 
 struct NoTiming {
@@ -313,7 +357,7 @@ struct NoTiming {
 
 int check_stream(ddh_stream_t s) {
   if (!s) return DDH_EINVAL;
-  if (!s->alive()) return DDH_ESTATE;
+  if (!is_live(s)) return DDH_ESTATE;
   return DDH_OK;
 }
 
@@ -398,7 +442,7 @@ int ddh_default_params(int N, ddh_params* p) {
 
 // Device allocation of one stream (one hipMalloc): offsets of its buffers.
 struct StreamLayout {
-  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, total;
+  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, geo, total;
   explicit StreamLayout(int N) {
     const size_t px = (size_t)N * N;
     const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
@@ -420,6 +464,7 @@ struct StreamLayout {
     desc = take(sizeof(StreamDesc));
     dptr = take(sizeof(StreamDesc*));
     diag = take(kDiagParts * 3 * sizeof(double) + 64);
+    geo = take(px);  // aperture bytes of a stream created with an aperture array
     total = off;
   }
 };
@@ -430,26 +475,108 @@ int ddh_stream_bytes(int N, unsigned long long* bytes) {
   return DDH_OK;
 }
 
-int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
+// Host copy of an aperture array (host or device memory), validated: every
+// value 0 or 1, at least one 1.
+static int read_aperture(const float* a, int N, std::vector<unsigned char>* mask) {
+  const size_t n = (size_t)N * N;
+  std::vector<float> h(n);
+  hipPointerAttribute_t at{};
+  bool on_device = false;
+  if (hipPointerGetAttributes(&at, a) == hipSuccess)
+    on_device = at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+  else
+    (void)hipGetLastError();  // plain host memory is not known to HIP: not an error here
+  if (on_device)
+    DDH_CHECK(hipMemcpy(h.data(), a, n * sizeof(float), hipMemcpyDeviceToHost));
+  else
+    memcpy(h.data(), a, n * sizeof(float));
+  mask->assign(n, 0);
+  size_t inside = 0;
+  for (size_t k = 0; k < n; ++k) {
+    if (h[k] == 1.0f) {
+      (*mask)[k] = 1;
+      ++inside;
+    } else if (h[k] != 0.0f) {  // also NaN
+      return DDH_EINVAL;
+    }
+  }
+  return inside ? DDH_OK : DDH_EINVAL;
+}
+
+// Plane-fit moments over the aperture (exact sums over integer coordinates,
+// in double): n, sum di, sum dj, sum di^2, sum di dj, sum dj^2 with
+// di = i - c, dj = j - c, c = (N-1)/2, and the inverse of the symmetric
+// normal matrix; returns false (inverse left zero) when it is singular.
+static bool aperture_moments(int N, const std::vector<unsigned char>& inside, double* mom, double* minv) {
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  const double c = 0.5 * (N - 1);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (!inside[(size_t)i * N + j]) continue;
+      const double a = i - c, b = j - c;
+      m[0] += 1;
+      m[1] += a;
+      m[2] += b;
+      m[3] += a * a;
+      m[4] += a * b;
+      m[5] += b * b;
+    }
+  memcpy(mom, m, sizeof m);
+  // symmetric inverse by cofactors (the plane fit's normal equations)
+  const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+  const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+  const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+  const double det = a00 * c00 + a01 * c01 + a02 * c02;
+  const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
+  for (int q = 0; q < 6; ++q) minv[q] = det != 0.0 ? inv[q] : 0.0;
+  return det != 0.0;
+}
+
+int ddh_init_stream(const ddh_params* p, const float* aperture, void* hip_stream, ddh_stream_t* out) {
   if (!out) return DDH_EINVAL;
-  int rc = validate(p);
+  int rc = validate(p, aperture == nullptr);
   if (rc != DDH_OK) return rc;
+  const int N = p->N;
+  const float d2 = p->pupil_diameter * p->pupil_diameter;
+  // the aperture: the caller's array (validated before any device work) or
+  // the circle of the given diameter
+  std::vector<unsigned char> inside;
+  if (aperture) {
+    rc = read_aperture(aperture, N, &inside);
+    if (rc != DDH_OK) return rc;
+  } else {
+    inside = circle_mask(N, d2);
+  }
+  double mom[6], minv[6];
+  // an aperture array must fix the plane of RemoveTipTilt (three pixels not on one line)
+  if (!aperture_moments(N, inside, mom, minv) && aperture) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int dev = 0;
   DDH_CHECK(hipGetDevice(&dev));
   float2* tw_all = nullptr;
   rc = ensure_twiddles(dev, &tw_all);
   if (rc != DDH_OK) return rc;
-  const int N = p->N;
   const unsigned char* geo = nullptr;
-  rc = ensure_geometry(dev, N, p->pupil_diameter * p->pupil_diameter, &geo);
-  if (rc != DDH_OK) return rc;
+  if (!aperture) {
+    rc = ensure_geometry(dev, N, d2, &geo);
+    if (rc != DDH_OK) return rc;
+  }
   const StreamLayout lay(N);
   const size_t o_r0 = lay.r0, o_r1 = lay.r1, o_p0 = lay.p0, o_p1 = lay.p1, o_T = lay.T, o_U = lay.U, o_bb = lay.bb;
   const size_t o_part = lay.part, o_scal = lay.scal, o_desc = lay.desc, o_dptr = lay.dptr, o_diag = lay.diag;
   char* mem = nullptr;
   hipError_t e = hipMalloc(&mem, lay.total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(stream)");
+  if (aperture) {
+    // the stream's own aperture bytes
+    const std::vector<unsigned char> g = geometry_bytes(N, inside);
+    e = hipMemcpy(mem + lay.geo, g.data(), g.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(mem);
+      return hip_fail(e, "hipMemcpy(aperture)");
+    }
+    geo = (const unsigned char*)(mem + lay.geo);
+  }
   ddh_stream_t s = new ddh_stream_s();
   s->prm = *p;
   s->N = N;
@@ -470,7 +597,6 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   h.geo = geo;
   h.N = N;
   h.cur = 0;
-  h.pupil_d2 = p->pupil_diameter * p->pupil_diameter;
   h.sigma2 = p->sigma_w2;
   h.lam = p->lambda;
   h.alpha = p->alpha;
@@ -496,32 +622,8 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
     h.qg_lc = -256.0f;
     h.qg_inv_sp *= 0.5f;
   }
-  // pupil moments (exact sums over integer coordinates, in double)
-  {
-    double m[6] = {0, 0, 0, 0, 0, 0};
-    const double c = 0.5 * (N - 1);
-    const float d2 = h.pupil_d2;
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) {
-        const int di2 = 2 * i - N + 1, dj2 = 2 * j - N + 1;
-        if ((float)(di2 * di2 + dj2 * dj2) > d2) continue;
-        const double a = i - c, b = j - c;
-        m[0] += 1;
-        m[1] += a;
-        m[2] += b;
-        m[3] += a * a;
-        m[4] += a * b;
-        m[5] += b * b;
-      }
-    memcpy(h.mom, m, sizeof m);
-    // symmetric inverse by cofactors (the plane fit's normal equations)
-    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
-    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
-    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
-    const double det = a00 * c00 + a01 * c01 + a02 * c02;
-    const double inv[6] = {c00 / det, c01 / det, c02 / det, c11 / det, c12 / det, c22 / det};
-    for (int q = 0; q < 6; ++q) h.minv[q] = det != 0.0 ? inv[q] : 0.0;
-  }
+  memcpy(h.mom, mom, sizeof mom);
+  memcpy(h.minv, minv, sizeof minv);
   s->d = (StreamDesc*)(mem + o_desc);
   s->dptr = (StreamDesc**)(mem + o_dptr);
   s->diag = (double*)(mem + o_diag);
@@ -544,6 +646,7 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
   if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
   const char* g = getenv("DDH_SINGLE_GRAPH");
   s->use_graph = (g && g[0] == '1');
+  live_add(s);
   *out = s;
   return DDH_OK;
 }
@@ -551,12 +654,12 @@ int ddh_init_stream(const ddh_params* p, void* hip_stream, ddh_stream_t* out) {
 int ddh_destroy_stream(ddh_stream_t s) {
   int rc = check_stream(s);
   if (rc != DDH_OK) return rc;
+  live_remove(s);
   set_device_of(s->device);
   (void)hipDeviceSynchronize();
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
   (void)hipFree(s->mem);
-  s->magic = kDead;
   delete s;
   return DDH_OK;
 }
@@ -637,7 +740,7 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const size_t bytes = sizeof(float) * (size_t)s->N * s->N;
   DDH_CHECK(hipMemcpyAsync(s->h.r[s->parity], r, bytes, hipMemcpyDeviceToDevice, st));
-  DDH_CHECK(launch_copy_pupil(s->h.phi[s->parity], phi, s->N, s->h.pupil_d2, st));
+  DDH_CHECK(launch_copy_pupil(s->h.phi[s->parity], phi, s->N, s->h.geo, st));
   s->n = n;
   return DDH_OK;
 }
@@ -812,13 +915,15 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
     delete b;
     return hip_fail(e, "batch setup");
   }
+  live_add(b);
   *out = b;
   return DDH_OK;
 }
 
 int ddh_batch_destroy(ddh_batch_t b) {
   if (!b) return DDH_EINVAL;
-  if (!b->alive()) return DDH_ESTATE;
+  if (!is_live(b)) return DDH_ESTATE;
+  live_remove(b);
   set_device_of(b->device);
   (void)hipDeviceSynchronize();
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -830,14 +935,13 @@ int ddh_batch_destroy(ddh_batch_t b) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipEvent_t ev : b->pool) (void)hipEventDestroy(ev);
   (void)hipFree(b->dptrs);
-  b->magic = kDead;
   delete b;
   return DDH_OK;
 }
 
 int ddh_batch_set_timing(ddh_batch_t b, int enable) {
   if (!b) return DDH_EINVAL;
-  if (!b->alive()) return DDH_ESTATE;
+  if (!is_live(b)) return DDH_ESTATE;
   b->timing = enable != 0;
   for (int k = 0; k < KK_COUNT; ++k) {
     b->acc_ms[k] = 0;
@@ -889,9 +993,9 @@ static int enqueue_lanes(ddh_batch_t b, hipStream_t st) {
 
 int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
   if (!b || !y) return DDH_EINVAL;
-  if (!b->alive()) return DDH_ESTATE;
+  if (!is_live(b)) return DDH_ESTATE;
   for (int i = 0; i < b->total; ++i) {
-    if (!b->streams[i]->alive()) return DDH_ESTATE;
+    if (!is_live(b->streams[i])) return DDH_ESTATE;
     if (!y[i]) return DDH_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -979,13 +1083,15 @@ int ddh_server_create(int max_streams, ddh_server_t* out) {
     delete v;
     return hip_fail(e, "ddh_server_create");
   }
+  live_add(v);
   *out = v;
   return DDH_OK;
 }
 
 int ddh_server_destroy(ddh_server_t v) {
   if (!v) return DDH_EINVAL;
-  if (!v->alive()) return DDH_ESTATE;
+  if (!is_live(v)) return DDH_ESTATE;
+  live_remove(v);
   set_device_of(v->device);
   (void)hipDeviceSynchronize();
   for (int l = 0; l < 4; ++l) {
@@ -994,14 +1100,13 @@ int ddh_server_destroy(ddh_server_t v) {
   }
   (void)hipEventDestroy(v->fork);
   (void)hipFree(v->list);
-  v->magic = kDead;
   delete v;
   return DDH_OK;
 }
 
 int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream) {
   if (!v || (count > 0 && (!streams || !y))) return DDH_EINVAL;
-  if (!v->alive()) return DDH_ESTATE;
+  if (!is_live(v)) return DDH_ESTATE;
   if (count < 0 || count > v->max) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < count; ++i) {
@@ -1071,9 +1176,60 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
   return DDH_OK;
 }
 
+// One-shot batched frame step: a server per (device, HIP stream), created on
+// the first call with that pair and replaced by a larger one when a call
+// passes more streams than it holds; kept until the process ends.  Calls on
+// one HIP stream run in order, so the server's device list is reused safely.
+int ddh_step_batch(const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream) {
+  if (count < 0 || (count > 0 && (!streams || !y))) return DDH_EINVAL;
+  if (count > (1 << 20)) return DDH_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_stream(streams[i]);
+    if (rc != DDH_OK) return rc;
+    if (!y[i]) return DDH_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == streams[i]) return DDH_EINVAL;
+  }
+  if (count == 0) return DDH_OK;
+  const int dev = streams[0]->device;
+  for (int i = 1; i < count; ++i)
+    if (streams[i]->device != dev) return DDH_ESTATE;
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, ddh_server_t> servers;
+  ddh_server_t v = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, static_cast<hipStream_t>(hip_stream));
+    auto it = servers.find(key);
+    if (it != servers.end() && it->second->max < count) {
+      // grow: the old list may still be read by this HIP stream's queued work
+      int rc = set_device_of(dev);
+      if (rc != DDH_OK) return rc;
+      DDH_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+      ddh_server_destroy(it->second);
+      servers.erase(it);
+      it = servers.end();
+    }
+    if (it == servers.end()) {
+      int cap = 64;
+      while (cap < count) cap *= 2;
+      int cur = -1;
+      DDH_CHECK(hipGetDevice(&cur));
+      int rc = set_device_of(dev);
+      if (rc == DDH_OK) rc = ddh_server_create(cap, &v);
+      if (cur != dev) (void)hipSetDevice(cur);
+      if (rc != DDH_OK) return rc;
+      servers[key] = v;
+    } else {
+      v = it->second;
+    }
+  }
+  return ddh_server_step(v, streams, y, count, hip_stream);
+}
+
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n) {
   if (!b || !n) return DDH_EINVAL;
-  if (!b->alive()) return DDH_ESTATE;
+  if (!is_live(b)) return DDH_ESTATE;
   int rc = drain_timing(b);
   if (rc != DDH_OK) return rc;
   const int m = std::min(*n, (int)KK_COUNT);
@@ -1154,7 +1310,7 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
     ddh_params p;
     ddh_default_params(Ns[i], &p);
     ddh_stream_t s = nullptr;
-    rc = ddh_init_stream(&p, nullptr, &s);
+    rc = ddh_init_stream(&p, nullptr, nullptr, &s);
     if (rc == DDH_OK) ss.push_back(s);
     ys[i] = ybuf + off;
     off += (size_t)Ns[i] * Ns[i];
@@ -1266,7 +1422,7 @@ int ddh_autotune(int N, int count, int* cfg, double* us) {
   }
   for (int i = 0; i < count && rc == DDH_OK; ++i) {
     ddh_stream_t s = nullptr;
-    rc = ddh_init_stream(&p, nullptr, &s);
+    rc = ddh_init_stream(&p, nullptr, nullptr, &s);
     if (rc == DDH_OK) ss.push_back(s);
   }
   if (rc != DDH_OK) {

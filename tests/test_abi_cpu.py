@@ -51,7 +51,7 @@ def test_init_stream_validates_before_device_work(field, value):
     p = ddh.default_params(256)
     setattr(p, field, value)
     h = ctypes.c_void_p()
-    assert ddh.lib().ddh_init_stream(ctypes.byref(p), None, ctypes.byref(h)) == ddh.DDH_EINVAL
+    assert ddh.lib().ddh_init_stream(ctypes.byref(p), None, None, ctypes.byref(h)) == ddh.DDH_EINVAL
     assert h.value is None
 
 
@@ -62,7 +62,10 @@ def test_null_handles_are_rejected():
     assert L.ddh_em(None, y, None) == ddh.DDH_EINVAL
     assert L.ddh_get_phase(None, y, None) == ddh.DDH_EINVAL
     assert L.ddh_destroy_stream(None) == ddh.DDH_EINVAL
-    assert L.ddh_init_stream(None, None, None) == ddh.DDH_EINVAL
+    assert L.ddh_init_stream(None, None, None, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch(None, None, 1, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch(None, None, -1, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch(None, None, 0, None) == ddh.DDH_OK
     assert L.ddh_batch_create(None, 0, 0, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_step(None, None, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_destroy(None) == ddh.DDH_EINVAL
@@ -128,3 +131,67 @@ def test_autotune_mix_validates_before_device_work():
     assert L.ddh_autotune_mix(None, 3, None, None) == ddh.DDH_EINVAL
     assert L.ddh_autotune_mix(ns, 0, None, None) == ddh.DDH_EINVAL
     assert L.ddh_autotune_mix(ns, 3, None, None) == ddh.DDH_EINVAL  # 100 is not a supported size
+
+
+def _annulus(N, outer, inner):
+    import numpy as np
+    c = (N - 1) / 2.0
+    ii, jj = np.mgrid[0:N, 0:N]
+    d2 = (2 * ii - N + 1) ** 2 + (2 * jj - N + 1) ** 2
+    return ((d2 <= outer ** 2) & (d2 > inner ** 2)).astype(np.float32)
+
+
+@pytest.mark.parametrize("case", ["non_binary", "nan", "empty", "one_line"])
+def test_init_stream_rejects_bad_aperture_arrays_before_device_work(case):
+    """The aperture array (host memory here) is validated before any device
+    work: values must be 0 or 1, at least one pixel, and not all on one line
+    (the RemoveTipTilt plane would not be determined)."""
+    import numpy as np
+    N = 64
+    a = _annulus(N, N, N // 2)
+    if case == "non_binary":
+        a[10, 10] = 0.5
+    elif case == "nan":
+        a[20, 20] = np.nan
+    elif case == "empty":
+        a[:] = 0
+    else:
+        a[:] = 0
+        a[5, 3:40] = 1  # one row
+    p = ddh.default_params(N)
+    h = ctypes.c_void_p()
+    rc = ddh.lib().ddh_init_stream(ctypes.byref(p), ctypes.c_void_p(a.ctypes.data), None, ctypes.byref(h))
+    assert rc == ddh.DDH_EINVAL and h.value is None
+
+
+def test_aperture_array_skips_the_diameter_check():
+    """With an aperture array the diameter is not used, so a zero diameter
+    does not fail validation (the call then needs a device; without one it
+    stops at the first device call, not at the parameters)."""
+    N = 64
+    a = _annulus(N, N, N // 2)
+    p = ddh.default_params(N)
+    p.pupil_diameter = 0.0
+    h = ctypes.c_void_p()
+    rc = ddh.lib().ddh_init_stream(ctypes.byref(p), ctypes.c_void_p(a.ctypes.data), None, ctypes.byref(h))
+    assert rc != ddh.DDH_EINVAL
+
+
+def test_stale_handles_are_rejected_without_reading_them():
+    """A pointer that the library never handed out (or has destroyed) is
+    reported as a dead handle: handles are checked by membership in the
+    library's set of live handles, not by reading through the pointer."""
+    import numpy as np
+    L = ddh.lib()
+    junk = np.zeros(64, dtype=np.uint8)       # readable memory that is not a handle
+    h = ctypes.c_void_p(junk.ctypes.data)
+    y = ctypes.c_void_p(16)
+    assert L.ddh_step(h, y, None) == ddh.DDH_ESTATE
+    assert L.ddh_destroy_stream(h) == ddh.DDH_ESTATE
+    assert L.ddh_batch_destroy(h) == ddh.DDH_ESTATE
+    assert L.ddh_server_destroy(h) == ddh.DDH_ESTATE
+    arr = (ctypes.c_void_p * 1)(junk.ctypes.data)
+    ys = (ctypes.c_void_p * 1)(16)
+    assert L.ddh_step_batch(arr, ys, 1, None) == ddh.DDH_ESTATE
+    b = ctypes.c_void_p()
+    assert L.ddh_batch_create(arr, 1, 0, ctypes.byref(b)) == ddh.DDH_ESTATE
