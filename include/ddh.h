@@ -260,6 +260,24 @@ int ddh_server_step(ddh_server_t s, const ddh_stream_t* streams, const void* con
  * count > 0, a repeated stream, a NULL frame or count > 2^20. */
 int ddh_step_batch(const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream);
 
+/* ddh_step_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * frame on the same streams with the same per-stream results, bit for bit,
+ * but the call allocates nothing -- no device memory, no HIP streams, no
+ * host heap.  The device list of descriptor pointers that the frame's first
+ * launches fill and its later launches read is a fixed array of 4096 entries
+ * (32 KiB) that the library holds on every device it runs on until the
+ * process ends (its address is taken when the first stream is created on a
+ * device).  All groups of (n_k, N) run one after another on hip_stream
+ * (no internal HIP streams).  Every call on one device shares that array and
+ * leaves its contents behind: calls that overlap on one GPU (on different HIP
+ * streams, or from different host threads) race and must be serialised by
+ * the caller; calls queued on one HIP stream are ordered and safe.  Errors:
+ * DDH_EINVAL for count < 0 or count > 4096 (checked first), a NULL array with
+ * count > 0, a repeated stream or a NULL frame; DDH_ESTATE for a destroyed
+ * handle or streams on more than one device. */
+int ddh_step_batch_noalloc(const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream);
+
 /* -------------------------------------------------------- differentiation */
 
 /* Gradient of K unrolled DDH frames.  Starting from r = 0 and phi = phi0, the

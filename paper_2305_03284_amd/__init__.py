@@ -67,6 +67,7 @@ SIGNATURES = {
     "ddh_server_step": (_c_int, [_c_void_p, ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int,
                                  _c_void_p]),
     "ddh_step_batch": (_c_int, [ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int, _c_void_p]),
+    "ddh_step_batch_noalloc": (_c_int, [ctypes.POINTER(_c_void_p), ctypes.POINTER(_c_void_p), _c_int, _c_void_p]),
     "ddh_unrolled_grad": (_c_int, [ctypes.POINTER(Params), _c_int, ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p,
                                    _c_int, _c_void_p, ctypes.POINTER(GradOut), _c_void_p]),
     "ddh_unrolled_grad_batch": (_c_int, [ctypes.POINTER(Params), _c_int, _c_int, ctypes.POINTER(_c_void_p),

@@ -19,6 +19,15 @@
 
 using namespace ddh;
 
+// Device list of stream-descriptor pointers for ddh_step_batch_noalloc (the
+// batched step for callers that cannot allocate): a file-scope device array,
+// of which every device that runs the library holds one copy until the
+// process ends.  Host code never uses its name as an address: the address on
+// each device is taken once, at the first stream creation on that device
+// (ensure_scratch), and only that address reaches kernels.
+constexpr int kNoAllocMaxStreams = 4096;
+static __device__ __align__(256) StreamDesc* scratch[kNoAllocMaxStreams];
+
 namespace {
 
 constexpr int kMaxDev = 64;
@@ -44,6 +53,30 @@ bool is_live(const void* h) {
   return g_live.count(h) != 0;
 }
 float2* g_tw[kMaxDev] = {nullptr};
+
+std::mutex g_scratch_mu;
+StreamDesc** g_scratch[kMaxDev] = {nullptr};
+constexpr int FRAME_CHUNK = 64;  // streams per stats launch filled from stack arrays
+
+int hip_fail(hipError_t e, const char* what);
+
+// The device address of `scratch` on device dev (which must be current).
+int ensure_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDev) return DDH_EDEVICE;
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<StreamDesc**>(ptr);
+  }
+  return DDH_OK;
+}
+
+StreamDesc** scratch_of(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDev ? g_scratch[dev] : nullptr;
+}
 
 int hip_fail(hipError_t e, const char* what) {
   char buf[256];
@@ -555,6 +588,8 @@ int ddh_init_stream(const ddh_params* p, const float* aperture, void* hip_stream
   DDH_CHECK(hipGetDevice(&dev));
   float2* tw_all = nullptr;
   rc = ensure_twiddles(dev, &tw_all);
+  if (rc != DDH_OK) return rc;
+  rc = ensure_scratch(dev);
   if (rc != DDH_OK) return rc;
   const unsigned char* geo = nullptr;
   if (!aperture) {
@@ -1225,6 +1260,79 @@ int ddh_step_batch(const ddh_stream_t* streams, const void* const* y, int count,
     }
   }
   return ddh_server_step(v, streams, y, count, hip_stream);
+}
+
+// ddh_step_batch without any allocation: the device list of descriptor
+// pointers is the file-scope `scratch` array of the streams' device (filled
+// by the frame's first launches from their arguments, read by the later
+// ones), every group of (n_k, N) runs on the caller's HIP stream, and the
+// host side uses fixed-size stack arrays only.
+int ddh_step_batch_noalloc(const ddh_stream_t* streams, const void* const* y, int count, void* hip_stream) {
+  if (count < 0 || count > kNoAllocMaxStreams) return DDH_EINVAL;
+  if (count > 0 && (!streams || !y)) return DDH_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_stream(streams[i]);
+    if (rc != DDH_OK) return rc;
+    if (!y[i]) return DDH_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == streams[i]) return DDH_EINVAL;
+  }
+  if (count == 0) return DDH_OK;
+  const int dev = streams[0]->device;
+  for (int i = 1; i < count; ++i)
+    if (streams[i]->device != dev) return DDH_ESTATE;
+  StreamDesc** list = scratch_of(dev);  // set when the first stream was created on dev
+  if (!list) return DDH_ESTATE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int pos = 0, prev_nk = 0;
+  for (;;) {
+    // next distinct n_k, ascending
+    int nk = 0;
+    for (int i = 0; i < count; ++i) {
+      const int v = streams[i]->prm.n_k;
+      if (v > prev_nk && (nk == 0 || v < nk)) nk = v;
+    }
+    if (nk == 0) break;
+    for (int N : {64, 128, 256, 512}) {
+      Group g{N, 0, 0, tiles_for(N), nullptr};
+      const float2* ys[FRAME_CHUNK];
+      int curs[FRAME_CHUNK];
+      StreamDesc* ds[FRAME_CHUNK];
+      int m = 0;
+      auto flush = [&]() -> int {
+        if (m == 0) return DDH_OK;
+        const hipError_t e = launch_stats(list + pos + g.count, m, N, 1, ys, curs, ds, st);
+        if (e != hipSuccess) return hip_fail(e, "launch_stats");
+        g.count += m;
+        m = 0;
+        return DDH_OK;
+      };
+      for (int i = 0; i < count; ++i) {
+        const ddh_stream_t s = streams[i];
+        if (s->prm.n_k != nk || s->N != N) continue;
+        ys[m] = static_cast<const float2*>(y[i]);
+        curs[m] = s->parity;
+        ds[m] = s->d;
+        g.tw = s->tw;
+        if (++m == FRAME_CHUNK) {
+          int rc = flush();
+          if (rc != DDH_OK) return rc;
+        }
+      }
+      int rc = flush();
+      if (rc != DDH_OK) return rc;
+      if (g.count == 0) continue;
+      rc = enqueue_iters(list + pos, &g, 1, nk, 1, st, NoTiming{});
+      if (rc != DDH_OK) return rc;
+      pos += g.count;
+    }
+    prev_nk = nk;
+  }
+  for (int i = 0; i < count; ++i) {
+    streams[i]->parity = (streams[i]->parity + streams[i]->prm.n_k) & 1;
+    streams[i]->n++;
+  }
+  return DDH_OK;
 }
 
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n) {

@@ -66,6 +66,10 @@ def test_null_handles_are_rejected():
     assert L.ddh_step_batch(None, None, 1, None) == ddh.DDH_EINVAL
     assert L.ddh_step_batch(None, None, -1, None) == ddh.DDH_EINVAL
     assert L.ddh_step_batch(None, None, 0, None) == ddh.DDH_OK
+    assert L.ddh_step_batch_noalloc(None, None, 1, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch_noalloc(None, None, -1, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch_noalloc(None, None, 4097, None) == ddh.DDH_EINVAL
+    assert L.ddh_step_batch_noalloc(None, None, 0, None) == ddh.DDH_OK
     assert L.ddh_batch_create(None, 0, 0, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_step(None, None, None) == ddh.DDH_EINVAL
     assert L.ddh_batch_destroy(None) == ddh.DDH_EINVAL
