@@ -45,7 +45,10 @@ def parse():
     p.add_argument("--latency-frames", type=int, default=200)
     p.add_argument("--plain-steps", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-frames", type=int, default=120)
+    p.add_argument("--cpu-frames", type=int, default=150, help="successive frames of one stream for the oracle "
+                   "baseline and the Strehl comparison")
+    p.add_argument("--cpu-frames-per-core", type=int, default=30)
+    p.add_argument("--mixed-steps", type=int, default=100)
     p.add_argument("--no-extras", action="store_true", help="only the timed batched step (for profiling)")
     p.add_argument("--autotune", action="store_true", help="time every tiling first and keep the fastest")
     p.add_argument("--autotune-mix", action="store_true",
@@ -53,6 +56,8 @@ def parse():
     p.add_argument("--tiles", type=str, default=None, help="row_lines,col_width,mstep_h,mstep_w for every N")
     p.add_argument("--graph", action="store_true", help="replay the batched step as a HIP graph (eager launches "
                    "are the default: they measured faster)")
+    p.add_argument("--worklist", action="store_true", help="run the batched step as the persistent work-list "
+                   "launch (stats, row and column passes of all streams as one work list) plus the M-step")
     p.add_argument("--lanes", type=int, default=0, help="HIP streams of the batch: 0 = one per distinct N (default), "
                    "1-8 = that many, balanced by pixels")
     p.add_argument("--serve", action="store_true", help="instead: the continuous-batching request loop (32 streams "
@@ -93,13 +98,16 @@ def kernel_bytes(N, fill):
     definition must read and the outputs it must write (arrays used only on
     the pupil counted with the pupil fill fraction)."""
     f = fill
-    return {
+    kb = {
         "stats": 8 + 4 * f,                     # y; phi on the pupil
         "row_ifft": 12 * f + 8,                 # y, phi on the pupil; T
         "col_fused": 8 + 4 + 8 + 4,             # T, r; U, |b|^2
         "row_fft": 8 + 12 * f + 8 * f,          # U; y, phi on the pupil; (kappa, theta~) on the pupil
         "m_step": 4 + 4 + 12 * f + 4 + 4 * f,   # r, |b|^2, phi, (kappa, theta~); r, phi (pupil)
     }
+    # the work-list launch runs the first four as one kernel
+    kb["frame_worklist"] = kb["stats"] + kb["row_ifft"] + kb["col_fused"] + kb["row_fft"]
+    return kb
 
 
 def mstep_ops(fill):
@@ -131,30 +139,76 @@ def recorded_traffic(kernel_kind, tiles):
     return int(rec["traffic_bytes"])
 
 
-def oracle_baseline(specs, frames, n_frames_cpu):
-    """FP64 oracle on the host: the first stream of the workload, frames
-    cycled as on the GPU, one thread."""
+def oracle_params(sigma_w2):
+    from oracle import ddh as O
+    import ddh_synth as synth
+    v = synth.DEFAULT_PARAMS
+    return O.Params(sigma_w2=sigma_w2, lam=v["lam"], alpha=v["alpha"], n_k=v["n_k"], qg_q=v["qg_q"],
+                    qg_T=v["qg_T"], qg_sigma=v["qg_sigma"], beta_phi=v["beta_phi"], r_floor=v["r_floor"])
+
+
+def oracle_baseline(spec, ys, truths):
+    """FP64 oracle on the host, one thread: the DDH frames ys (uncycled) of one
+    stream of the workload from the zero state.  Only the frames are timed;
+    the peak Strehl of every frame's phase is computed outside the timing."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ddh as O
+    from oracle import metrics as M
+    import ddh_synth as synth
+    st = synth.Stream(spec)
+    prm = oracle_params(st.sigma_w2)
+    a = O.aperture(spec.N)
+    r = np.zeros((spec.N, spec.N))
+    phi = np.zeros((spec.N, spec.N))
+    dt = 0.0
+    strehl = []
+    with threadpool_limits(limits=1):
+        for y, truth in zip(ys, truths):
+            t0 = time.perf_counter()
+            r, phi = O.ddh_frame(r, phi, y.astype(np.complex128), a, prm)
+            dt += time.perf_counter() - t0
+            strehl.append(M.strehl(phi, truth, a))
+    base = {"value": len(ys) * prm.n_k / dt, "unit": "EM iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(ys)} successive DDH frames (N_k={prm.n_k}, not cycled) of one N={spec.N} stream of the "
+                      f"workload from the zero state, FP64 NumPy, 1 thread, {dt:.1f} s of frame time"}
+    return base, strehl
+
+
+def _oracle_worker(job):
+    """One process of the all-core baseline: frames of its own stream."""
+    spec, n_frames = job
     from threadpoolctl import threadpool_limits
     from oracle import ddh as O
     import ddh_synth as synth
-    sp = specs[0]
-    st = synth.Stream(sp)
-    v = synth.DEFAULT_PARAMS
-    prm = O.Params(sigma_w2=st.sigma_w2, lam=v["lam"], alpha=v["alpha"], n_k=v["n_k"], qg_q=v["qg_q"],
-                   qg_T=v["qg_T"], qg_sigma=v["qg_sigma"], beta_phi=v["beta_phi"], r_floor=v["r_floor"])
-    a = O.aperture(sp.N)
-    r = np.zeros((sp.N, sp.N))
-    phi = np.zeros((sp.N, sp.N))
-    ys = [f.astype(np.complex128) for f in frames[0]]
+    st = synth.Stream(spec)
+    prm = oracle_params(st.sigma_w2)
+    a = O.aperture(spec.N)
+    ys = [st.frame(n).astype(np.complex128) for n in range(n_frames)]
+    r = np.zeros((spec.N, spec.N))
+    phi = np.zeros((spec.N, spec.N))
     with threadpool_limits(limits=1):
-        r, phi = O.ddh_frame(r, phi, ys[0], a, prm)  # warm-up
         t0 = time.perf_counter()
-        for k in range(n_frames_cpu):
-            r, phi = O.ddh_frame(r, phi, ys[k % len(ys)], a, prm)
-        dt = time.perf_counter() - t0
-    return {"value": n_frames_cpu * prm.n_k / dt, "unit": "EM iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_frames_cpu} DDH frames (N_k={prm.n_k}) of one N={sp.N} stream of the workload, "
-                      f"FP64 NumPy, 1 thread, {dt:.1f} s"}
+        for y in ys:
+            r, phi = O.ddh_frame(r, phi, y, a, prm)
+        t1 = time.perf_counter()
+    return n_frames * prm.n_k, t0, t1
+
+
+def oracle_all_cores(specs, n_frames):
+    """The oracle on every host core at once: one process per core, each on
+    its own stream of the workload (streams are independent), one thread per
+    process.  Throughput = all timed frames / the span from the first start to
+    the last end."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, 16, len(specs))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(specs[i], n_frames) for i in range(cores)])
+    frames = sum(r[0] for r in res)
+    span = max(r[2] for r in res) - min(r[1] for r in res)
+    return {"value": frames / span, "unit": "EM iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} processes x {n_frames} DDH frames, each its own N={specs[0].N} stream of the "
+                      f"workload, FP64 NumPy, 1 thread per process, {span:.1f} s span"}
 
 
 def serve_main(args):
@@ -505,7 +559,7 @@ def main():
     dev_frames = [[torch.from_numpy(frames[i][k]).cuda() for i in range(S)] for k in range(args.frames)]
     ptrs = [[t.data_ptr() for t in dev_frames[k]] for k in range(args.frames)]
     streams = [D.Stream(sp.N, gpu_params(D, sp.N, sims[i].sigma_w2)) for i, sp in enumerate(specs)]
-    batch = D.Batch(streams, graph=args.graph, lanes=args.lanes)
+    batch = D.Batch(streams, graph=args.graph, lanes=args.lanes, worklist=args.worklist)
     torch.cuda.synchronize()
 
     step = 0
@@ -538,7 +592,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "streams": S, "N": args.N if args.workload == "uniform" else "mixed",
                    "n_k": 1, "pixels_per_step": px_total, "frames_cycled": args.frames,
-                   "launch": "graph" if args.graph else "eager", "lanes": "one per N" if args.lanes == 0 else args.lanes,
+                   "launch": ("graph" if args.graph else "eager") + (", work list" if args.worklist else ""),
+                   "lanes": "one per N" if args.lanes == 0 else args.lanes,
                    "tiles": {str(k): v for k, v in tiles.items()}},
     }
 
@@ -593,7 +648,7 @@ def main():
                                "unit": "GB/s", "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
                                "traffic": recorded_traffic(dom, tiles.get(args.N, ()))}
         step_bytes_floor = 56 * px_total  # compulsory + one global round trip per 2-D FFT
-        step_bytes_alg = sum(kb[k] for k in kb) * px_total
+        step_bytes_alg = sum(kb[k] for k in kb if k != "frame_worklist") * px_total
         out["kernels"] = kernels
         out["step"] = {"us": round(1e3 * ms_per_step, 2), "sum_of_timed_kernels_us": round(eager_step_us, 2),
                        "floor_bytes": step_bytes_floor, "alg_bytes": int(step_bytes_alg),
@@ -648,21 +703,131 @@ def main():
                                            "end_to_end_note": "with the H2D copy of y from pinned host memory"}
         s1.close()
 
-        # ---- Strehl of the batch against the truth of the frame index each
-        # stream saw last (frames are cycled, so this is indicative only)
-        strehls = []
-        for i in range(min(S, 16)):
-            truth = torch.from_numpy(sims[i].phase((step - 1) % args.frames).astype(np.float32)).cuda()
-            strehls.append(streams[i].strehl(truth))
-        out["strehl_mean_first16"] = round(float(np.mean(strehls)), 4)
+        # ---- the same batched step with the other launch structure (work list
+        # or the five launches per iteration), same streams and frames
+        obatch = D.Batch(streams, graph=args.graph, lanes=args.lanes, worklist=not args.worklist)
+        for _ in range(args.warmup):
+            obatch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        torch.cuda.synchronize()
+        to = time.perf_counter()
+        for _ in range(args.steps):
+            obatch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        torch.cuda.synchronize()
+        dto = time.perf_counter() - to
+        obatch.set_timing(True)
+        for _ in range(args.timing_steps):
+            obatch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        o_times = {k_: round(1e3 * ms_ / c_, 3) for k_, (ms_, c_) in obatch.stage_times().items() if c_}
+        obatch.close()
+        out["worklist" if not args.worklist else "five_launches"] = {
+            "value": round(S * args.steps / dtg_guard(dto), 1), "unit": "EM iters/s",
+            "ms_per_step": round(1e3 * dto / args.steps, 4), "kernel_avg_us": o_times,
+            "note": "same streams and frames; " + ("persistent work-list launch (stats, row and column passes as "
+                                                   "one work list) + M-step" if not args.worklist else
+                                                   "stats, row, column, row, M-step launches")}
+
+        # ---- the same batched step replayed as a HIP graph (same streams, frames)
+        gbatch = D.Batch(streams, graph=True, lanes=args.lanes, worklist=args.worklist)
+        for _ in range(args.warmup):
+            gbatch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            gbatch.step_ptrs(ptrs[step % args.frames])
+            step += 1
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - tg
+        gbatch.close()
+        out["graph_replay"] = {"value": round(S * args.steps / dtg, 1), "unit": "EM iters/s",
+                               "ms_per_step": round(1e3 * dtg / args.steps, 4),
+                               "note": "same batch, step captured once as a HIP graph and replayed"}
+
+        # ---- whole step against HBM and against a device copy of the step's footprint
+        foot = max(step_bytes_floor, 448 * 2 ** 20)
+        csrc = torch.empty(foot // 8, dtype=torch.float32, device="cuda").fill_(1.0)
+        cdst = torch.empty_like(csrc)
+        ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cdst.copy_(csrc)
+        torch.cuda.synchronize()
+        ce0.record()
+        for _ in range(10):
+            cdst.copy_(csrc)
+        ce1.record()
+        ce1.synchronize()
+        copy_gbs = 2 * (foot // 8) * 4 * 10 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+        del csrc, cdst
+        step_gbs = step_bytes_floor / (ms_per_step * 1e-3) / 1e9
+        out["step_roofline"] = {"bound": "hbm", "floor_bytes_per_step": step_bytes_floor,
+                                "floor_B_per_px": 56, "achieved": round(step_gbs, 1), "unit": "GB/s",
+                                "peak": HBM_PEAK_GBS, "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                                "copy_GB_s": round(copy_gbs, 1), "copy_bytes_moved": 2 * (foot // 8) * 4,
+                                "frac_of_copy": round(step_gbs / copy_gbs, 4), "target_frac": 0.5,
+                                "met": bool(step_gbs / HBM_PEAK_GBS >= 0.5)}
+
+        # ---- Strehl on successive (uncycled) frames of one stream: GPU and oracle
+        sp0 = specs[0]
+        n_q = args.cpu_frames
+        q_frames = [sims[0].frame(n) for n in range(n_q)]
+        q_truth = [sims[0].phase(n) for n in range(n_q)]
+        sq = D.Stream(sp0.N, gpu_params(D, sp0.N, sims[0].sigma_w2))
+        s_zero = D.Stream(sp0.N, gpu_params(D, sp0.N, sims[0].sigma_w2))  # never stepped: phase 0 (uncorrected)
+        s_gpu, s_unc = [], []
+        for n in range(n_q):
+            sq.step(torch.from_numpy(q_frames[n]).cuda())
+            tr = torch.from_numpy(q_truth[n].astype(np.float32)).cuda()
+            s_gpu.append(sq.strehl(tr))
+            s_unc.append(s_zero.strehl(tr))
+        sq.close()
+        s_zero.close()
+        strehl = {"stream": f"workload stream 0 (N={sp0.N}, D/r0={sp0.d_over_r0:.2f}, SNR={sp0.snr:.2f})",
+                  "frames": n_q, "gpu_mean_last50": round(float(np.mean(s_gpu[-50:])), 4),
+                  "uncorrected_mean_last50": round(float(np.mean(s_unc[-50:])), 4)}
 
         if not args.no_cpu_baseline:
-            out["cpu_baseline"] = oracle_baseline(specs, frames, args.cpu_frames)
+            base, s_orc = oracle_baseline(sp0, q_frames, q_truth)
+            out["cpu_baseline"] = base
             out["cpu_baseline"]["host_cpu"] = _cpu_model()
             out["cpu_baseline"]["host_cpu_count"] = os.cpu_count()
+            strehl["oracle_mean_last50"] = round(float(np.mean(s_orc[-50:])), 4)
+            strehl["max_abs_diff_gpu_oracle"] = round(float(np.max(np.abs(np.array(s_gpu) - np.array(s_orc)))), 5)
+            out["cpu_baseline_all_cores"] = oracle_all_cores(specs, args.cpu_frames_per_core)
+        out["strehl"] = strehl
+
+        # ---- the mixed-size workload (64 streams, N 128/256/512 at 2:5:1), one lane per N
+        if args.workload == "uniform" and args.mixed_steps > 0:
+            mspecs = synth.batch_specs(count=64, config_id=2)
+            msims, mframes = make_inputs(mspecs, 4)
+            mdev = [[torch.from_numpy(mframes[i][k]).cuda() for i in range(len(mspecs))] for k in range(4)]
+            mptrs = [[t.data_ptr() for t in mdev[k]] for k in range(4)]
+            mstreams = [D.Stream(sp.N, gpu_params(D, sp.N, msims[i].sigma_w2)) for i, sp in enumerate(mspecs)]
+            mb = D.Batch(mstreams, graph=False, lanes=0)
+            for k in range(args.warmup):
+                mb.step_ptrs(mptrs[k % 4])
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            for k in range(args.mixed_steps):
+                mb.step_ptrs(mptrs[k % 4])
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - tm
+            mb.close()
+            for s_ in mstreams:
+                s_.close()
+            out["mixed_workload"] = {"value": round(len(mspecs) * args.mixed_steps / dtm, 1), "unit": "EM iters/s",
+                                     "ms_per_step": round(1e3 * dtm / args.mixed_steps, 4),
+                                     "workload": "64 streams, N in {128,256,512} at 2:5:1 (16/40/8), eager, one "
+                                                 "lane per N, 4 frames cycled",
+                                     "pixels_per_step": sum(sp.N * sp.N for sp in mspecs)}
     out["input_generation_s"] = round(t_gen, 1)
     batch.close()
     print(json.dumps(out), flush=True)
+
+
+def dtg_guard(dt):
+    return dt if dt > 0 else 1e-9
 
 
 def _cpu_model():

@@ -154,7 +154,9 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
 int ddh_frame_count(ddh_stream_t s, long long* n);
 
 /* Synchronise hip_stream and report whether the last frame submitted on s
- * was rejected (DDH_EDATA) or accepted (DDH_OK). */
+ * was rejected (DDH_EDATA) or accepted (DDH_OK), or whether a wait of the
+ * work-list step (DDH_BATCH_WORKLIST) gave up on s since the last call
+ * (DDH_EDEVICE; reported once). */
 int ddh_status(ddh_stream_t s, void* hip_stream);
 
 /* Grid size and parameters of a stream. */
@@ -192,6 +194,22 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
  * batch does not own the streams; destroy the batch before its streams. */
 #define DDH_BATCH_GRAPH 1
 #define DDH_BATCH_LANES(n) (((n) & 0xff) << 8)
+/* DDH_BATCH_WORKLIST: each EM iteration of a frame runs as one persistent
+ * work-list launch per N group -- the Normalize/RemoveTipTilt statistics,
+ * the first row DFT pass, the fused column pass and the second row pass of
+ * all the group's streams, as (stream, stage, tile) items that workgroups
+ * claim in dependency order from one queue per XCD, so that the stages of
+ * different streams overlap -- followed by the M-step launch (two launches
+ * per iteration instead of five).  Results are bit-identical to the default
+ * launches.  Every wait of an item on the previous stage of its stream is
+ * bounded; a wait that gives up lets the launch finish, and ddh_status then
+ * reports DDH_EDEVICE for that stream and clears its work-list control
+ * words; its state is then unspecified: restore it with ddh_set_state (which
+ * also clears those words) before its next frame.  DDH_BATCH_TEST_GIVEUP (with
+ * DDH_BATCH_WORKLIST; for tests of that failure path only) makes every such
+ * wait give up at once. */
+#define DDH_BATCH_WORKLIST 2
+#define DDH_BATCH_TEST_GIVEUP 4
 int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);
 int ddh_batch_destroy(ddh_batch_t b);
 
@@ -206,7 +224,8 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * (on input *n is the capacity of the arrays), the summed milliseconds ms[k]
  * and launch count calls[k] since timing was enabled, and its name to
  * names[k] (static strings).  Kinds: 0 stats, 1 finalize, 2 row-ifft,
- * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame start).  The combine of
+ * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame start), 7 frame_worklist
+ * (the persistent launch of a DDH_BATCH_WORKLIST batch).  The combine of
  * the stats partials runs inside the first row pass of a frame, and an eager
  * step passes the frame start to the stats kernel, so kinds 1 and 6 stay at
  * zero launches in a timed step. */
@@ -349,9 +368,13 @@ int ddh_get_tiles(int N, int* cfg);
 /* Autotune the tiling for grid size N on the current device: time every
  * candidate of each kernel on `count` temporary streams (synthetic frames
  * generated on the device), keep the fastest per kernel, and install it as with
- * ddh_set_tiles.  Writes the choice to cfg (4 ints) and the winners' average
- * kernel times in microseconds to us (4 doubles: both row passes together,
- * column pass, 0, M-step), either may be NULL.  Synchronises the device. */
+ * ddh_set_tiles.  Candidates are given to the timing batches only, on the
+ * tuner's own HIP stream: the process-wide tiling changes once, at the end, and
+ * other work on the device is not synchronised with while the tuner runs.
+ * Writes the choice to cfg (4 ints) and the winners' average kernel times in
+ * microseconds to us (4 doubles: both row passes together, column pass, 0,
+ * M-step), either may be NULL.  Returns when the tuning work has finished;
+ * on error the tiling in force before the call is kept. */
 int ddh_autotune(int N, int count, int* cfg, double* us);
 
 /* Autotune the tilings of a mix of sizes together: `count` temporary streams
@@ -359,14 +382,14 @@ int ddh_autotune(int N, int count, int* cfg, double* us);
  * the default lanes (one per N); the whole batched step is timed with HIP
  * events while each distinct size's row, column and M-step tilings are varied
  * in turn (sizes ascending), and a candidate replaces the current tiling only
- * if the step gets more than 1 % faster.  The result is installed as with
- * ddh_set_tiles.  cfgs (may be NULL) receives 4 ints per distinct size, sizes
+ * if the step gets more than 1 % faster.  Candidates are given to the timing
+ * batches only, on the tuner's own HIP stream; the result is installed, as
+ * with ddh_set_tiles, once at the end, so other batches and single-stream
+ * calls never run a candidate and are not synchronised with while the tuner
+ * runs.  cfgs (may be NULL) receives 4 ints per distinct size, sizes
  * ascending; step_us (may be NULL) the final step time in microseconds.
- * Synchronises the device.  The process-wide tilings change while the call
- * runs: batches created meanwhile by other threads may get a candidate
- * tiling (results do not depend on the tiling).  Errors: DDH_EINVAL (Ns
- * NULL, count outside 1..4096, an unsupported size), DDH_ENOMEM,
- * DDH_EDEVICE; on error the tilings in force before the call are restored. */
+ * Errors: DDH_EINVAL (Ns NULL, count outside 1..4096, an unsupported size),
+ * DDH_ENOMEM, DDH_EDEVICE; on error nothing is installed. */
 int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us);
 
 /* ------------------------------------------------------------------- misc */

@@ -172,7 +172,11 @@ def reference_gradient(phi0: np.ndarray, sigma_w: float, sigma_r: float, beta: f
     bt = torch.tensor(float(beta), dtype=_T, requires_grad=True)
     L = unrolled_loss(p0, sw, sr, bt, frames, phi_true, a, prm)
     L.backward()
-    return float(L.detach()), p0.grad.numpy().copy(), float(sw.grad), float(sr.grad), float(bt.grad)
+    # a parameter the loss does not reach (sigma_r with one frame: the phase
+    # step of a frame uses the Eq. (3) reflectance, not the r M-step's) has
+    # derivative zero; autograd leaves its grad unset
+    d = [float(x.grad) if x.grad is not None else 0.0 for x in (sw, sr, bt)]
+    return float(L.detach()), p0.grad.numpy().copy(), d[0], d[1], d[2]
 
 
 def oracle_loss(phi0: np.ndarray, sigma_w: float, sigma_r: float, beta: float, frames, phi_true, a,

@@ -21,6 +21,8 @@ DDH_EDEVICE = -3
 DDH_EDATA = -4
 DDH_ESTATE = -5
 DDH_BATCH_GRAPH = 1
+DDH_BATCH_WORKLIST = 2
+DDH_BATCH_TEST_GIVEUP = 4
 
 # every function the header declares, with its ctypes signature
 _c_int, _c_void_p, _c_double, _c_ll = ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong
@@ -241,9 +243,10 @@ class Stream:
         return n.value
 
     def status(self) -> int:
-        """DDH_OK or DDH_EDATA for the last submitted frame (synchronises)."""
+        """DDH_OK or DDH_EDATA for the last submitted frame, or DDH_EDEVICE if a
+        wait of a work-list batch gave up on this stream (synchronises)."""
         rc = lib().ddh_status(self.handle, _stream_ptr())
-        if rc not in (DDH_OK, DDH_EDATA):
+        if rc not in (DDH_OK, DDH_EDATA, DDH_EDEVICE):
             _check(rc, "ddh_status")
         return rc
 
@@ -278,11 +281,14 @@ class Stream:
 class Batch:
     """Several streams advanced together by one call per frame."""
 
-    def __init__(self, streams, graph: bool = True, lanes: int = 0):
+    def __init__(self, streams, graph: bool = True, lanes: int = 0, worklist: bool = False,
+                 test_giveup: bool = False):
         self.streams = list(streams)
         arr = (ctypes.c_void_p * len(self.streams))(*[s.handle.value for s in self.streams])
         h = ctypes.c_void_p()
         flags = (DDH_BATCH_GRAPH if graph else 0) | ((int(lanes) & 0xff) << 8)  # lanes 0: one per distinct N
+        if worklist:
+            flags |= DDH_BATCH_WORKLIST | (DDH_BATCH_TEST_GIVEUP if test_giveup else 0)
         _check(lib().ddh_batch_create(arr, len(self.streams), flags, ctypes.byref(h)), "ddh_batch_create")
         self._h = h
         self._ptrs = (ctypes.c_void_p * len(self.streams))()

@@ -19,8 +19,12 @@ SOURCES = ["ddh_kernels.hip", "ddh_runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DDH_OFFLOAD_ARCH", "gfx950")
-# packed FP32 instructions are disabled for all device code (see design notes)
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+# packed FP32 instructions are disabled for all device code (see design
+# notes); no implicit contraction of a*b+c into FMAs: explicit FMAs are
+# written where wanted, so a formula rounds the same in every kernel that
+# evaluates it (the persistent work-list kernel and the per-stage kernels
+# share their block bodies and give bit-identical results)
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + INCLUDE, "-I" + CSRC]
 

@@ -38,6 +38,10 @@ struct StreamDesc {
   // off the aperture.  Read-only: for a circular pupil shared by the streams
   // of one device, N and diameter; for an aperture array the stream's own.
   const unsigned char* geo;
+  // work-list control words (persistent frame kernel), CTL_WORDS unsigned:
+  // queue tickets and the finished-workgroup count (used in the first
+  // stream of a launch), this stream's stage counters and its give-up flag
+  unsigned* ctl;
   int N;
   int cur;             // index of the current state buffer at the start of a frame
   float sigma2, lam, alpha, beta, r_floor;
@@ -57,6 +61,15 @@ struct StreamDesc {
   double minv[6];
 };
 
+// Work-list control words of a stream (offsets in unsigned words; the
+// tickets, the stage counters and the flag sit on different cache lines).
+constexpr int CTL_TICKETS = 0;    // [0, 16): one ticket counter per XCD queue
+constexpr int CTL_FINISHED = 16;  // workgroups of the launch that have finished
+constexpr int CTL_STAGE = 32;     // [32, 36): completed items per stage (stats, row1, col, row2)
+constexpr int CTL_GIVEUP = 48;    // nonzero: a wait of this stream gave up
+constexpr int CTL_WORDS = 64;
+constexpr int CTL_MAX_QUEUES = 16;
+
 // Launch-site configuration (autotuned per N).
 struct TileConfig {
   int row_lines;   // lines per workgroup in the row kernels
@@ -66,7 +79,7 @@ struct TileConfig {
 };
 
 // Kernel kinds for per-stage timing.
-enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_BEGIN, KK_COUNT };
+enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_BEGIN, KK_FRAME, KK_COUNT };
 
 // Twiddle tables: exp(-2 pi i m / N) for m < N, for N = 64,128,256,512,
 // concatenated at offsets 0, 64, 192, 448 (total 960).
@@ -97,6 +110,18 @@ hipError_t launch_row2(StreamDesc* const* dptrs, int count, int N, const float2*
                        const TileConfig& tc, hipStream_t st);
 hipError_t launch_mstep(StreamDesc* const* dptrs, int count, int N, int k, int use_plane, int do_rinit,
                         const TileConfig& tc, hipStream_t st);
+// Persistent frame kernel: the stats (k == 0), row1, column and row2 stages
+// of `count` streams of one N as one work list (same results as the four
+// eager launches).  Frame start as for launch_stats (ys == nullptr: from the
+// descriptors).  ctl0: control words of the launch (the first stream's);
+// nq: XCD queues; lag: slots between consecutive stages of a stream;
+// spin_limit: polls before a wait gives up; giveup != 0 makes every wait
+// give up at once (failure-path tests).  whole_image: the M-step runs as
+// whole-image colour passes (the column and row2 stages then also write the
+// passes' working copies of r and phi).
+hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int mode,
+                        const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned* ctl0, int nq,
+                        int lag, unsigned spin_limit, int giveup, int whole_image, hipStream_t st);
 
 // Plain batched unitary 2D DFT (no fusion): rows into work, columns into out.
 hipError_t launch_fft2(int N, int count, const float2* in, float2* out, float2* work,

@@ -383,41 +383,34 @@ __global__ void k_begin(StreamDesc* const* dptrs, FrameArgs a, int count) {
 // registers), and the plane-fit sums of phi over the pupil.
 // grid (N*N/4096, streams), block 256
 // ---------------------------------------------------------------------------
-// use_args: 0 frame start from the descriptor; 1 from the arguments; 2 from
-// the arguments, and the descriptor pointers too, which block 0 of each
-// stream also stores in the device list dptrs for the later kernels.
+// Body of one stats block (item) of one stream: y is the stream's frame and
+// cur its current state buffer; writes the block's partial record.
 template <int N>
-__global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi, FrameArgs a, int use_args) {
-  const XcdBlock xb = xcd_block();
-  StreamDesc* const dp = use_args == 2 ? a.d[xb.strm] : dptrs[xb.strm];
-  const auto& D = desc_ref(dp);
-  __shared__ float red[6 * 16];
-  const int base = xb.item * STATS_PIX_PER_BLOCK;
+__device__ __forceinline__ void stats_body(const StreamDesc& D, const float2* y, int cur, int item, int with_phi,
+                                           float* red, int tid) {
+  const int base = item * STATS_PIX_PER_BLOCK;
   constexpr float c = 0.5f * (float)(N - 1);
   float2 v[16];
   float ph[16];
-  // frame start: from the arguments (block 0 stores them in the descriptor
-  // for the later kernels; no block of this launch reads them there) or from
-  // the descriptor
-  const float2* yv = use_args ? glb(a.y[xb.strm]) : glb(D.y);
-  const int cur = use_args ? a.cur[xb.strm] : D.cur;
+  const float2* yv = glb(y);
   const float* phi = glb(D.phi[cur]);
   // descriptor fields are read once, here: read inside the loops they would
   // be re-read after every store (which may alias the descriptor) and each
   // re-read waits for every memory operation in flight
   const auto geo = glb(D.geo);
+  float* out = glb(D.part) + item * PART_STRIDE;
   // every global read is issued up front: y, and phi on the pupil
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + threadIdx.x];
+  for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + tid];
   // phi is loaded at every pixel (branch-free: a load under a per-pixel
   // branch makes the compiler wait for all loads in flight at each join) and
   // masked to the pupil afterwards with the aperture bytes
   if (with_phi) {
     unsigned gg[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) ph[k] = phi[base + k * 256 + threadIdx.x];
+    for (int k = 0; k < 16; ++k) ph[k] = phi[base + k * 256 + tid];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) gg[k] = geo[base + k * 256 + threadIdx.x];
+    for (int k = 0; k < 16; ++k) gg[k] = geo[base + k * 256 + tid];
 #pragma unroll
     for (int k = 0; k < 16; ++k) ph[k] = geo_in(gg[k]) ? ph[k] : 0.0f;
   } else {
@@ -443,7 +436,7 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
   if (with_phi) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int idx = base + k * 256 + threadIdx.x;
+      const int idx = base + k * 256 + tid;
       const int i = idx / N, j = idx % N;
       const float p = ph[k];  // zero off the pupil
       ps[0] += p;
@@ -452,20 +445,38 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
     }
     block_sum<3>(ps, red);
   }
-  if (use_args && xb.item == 0 && threadIdx.x == 0) {
-    const auto d = glb(dp);
-    d->y = a.y[xb.strm];
-    d->cur = cur;
-    if (use_args == 2) glb(dptrs)[xb.strm] = dp;
-  }
-  if (threadIdx.x == 0) {
-    float* out = glb(D.part) + xb.item * PART_STRIDE;
+  if (tid == 0) {
     out[0] = mr;
     out[1] = mi;
     out[2] = m2[0];
     out[3] = ps[0];
     out[4] = ps[1];
     out[5] = ps[2];
+  }
+}
+
+// use_args: 0 frame start from the descriptor; 1 from the arguments; 2 from
+// the arguments, and the descriptor pointers too, which block 0 of each
+// stream also stores in the device list dptrs for the later kernels.
+template <int N>
+__global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi, FrameArgs a, int use_args) {
+  const XcdBlock xb = xcd_block();
+  StreamDesc* const dp = use_args == 2 ? a.d[xb.strm] : dptrs[xb.strm];
+  const auto& D = desc_ref(dp);
+  __shared__ float red[6 * 16];
+  // frame start: from the arguments (block 0 stores them in the descriptor
+  // for the later kernels; no block of this launch reads them there) or from
+  // the descriptor
+  const float2* y = use_args ? a.y[xb.strm] : D.y;
+  const int cur = use_args ? a.cur[xb.strm] : D.cur;
+  stats_body<N>(D, y, cur, xb.item, with_phi, red, threadIdx.x);
+  // after the body's descriptor reads (a store that may alias the
+  // descriptor would make later reads of it wait for all memory in flight)
+  if (use_args && xb.item == 0 && threadIdx.x == 0) {
+    const auto d = glb(dp);
+    d->y = a.y[xb.strm];
+    d->cur = cur;
+    if (use_args == 2) glb(dptrs)[xb.strm] = dp;
   }
 }
 
@@ -540,19 +551,18 @@ __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int w
 // inverse 1-D DFT along the row (unnormalised) -> T.
 // grid (N/LPW, streams), block LPW * N/E
 // ---------------------------------------------------------------------------
-template <int N, int LPW>
-__global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                             int k, int use_plane, int fin, int with_phi) {
+// Body of one row1 block (item = LPW rows) of one stream with frame yf and
+// current state buffer cur.  STAGE_TW: stage the twiddles into s_tw here
+// (otherwise the caller has).  lds holds LPW * RowLds<N>::STRIDE entries.
+template <int N, int LPW, bool STAGE_TW>
+__device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf, int cur, int item,
+                                          const float2* __restrict__ tw, int k, int use_plane, int fin, int with_phi,
+                                          float2* lds, float2* s_tw, float* scs, int tid) {
   constexpr int E = Plan<N>::E, T = N / E;
-  __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
-  __shared__ float2 s_tw[N];
-  __shared__ float scs[SC_COUNT];
-  const XcdBlock xb = xcd_block();
-  const auto& D = desc_ref(dptrs[xb.strm]);
-  const int line = threadIdx.x / T, t = threadIdx.x - line * T;
-  const int row = xb.item * LPW + line;
-  const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
-  const float2* y = glb(D.y) + row * N;
+  const int line = tid / T, t = tid - line * T;
+  const int row = item * LPW + line;
+  const float* phi = glb(D.phi[(cur + k) & 1]) + row * N;
+  const float2* y = glb(yf) + row * N;
   const auto geo = glb(D.geo) + row * N;  // read before any store (see k_stats)
   // global reads first (they depend on nothing computed here): the row of y,
   // phi and the aperture bytes, and the twiddle table into LDS
@@ -566,14 +576,15 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
     phv[i] = phi[n];
     gv[i] = geo[n];
   }
-  for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
+  if (STAGE_TW)
+    for (int i = tid; i < N; i += LPW * T) s_tw[i] = tw[i];
   float sc[SC_COUNT];
   if (fin) {
     // first EM iteration of a frame: every block combines the stats partials
     // itself (identical arithmetic in all blocks); block 0 publishes them
-    if (threadIdx.x < 64) combine_stats(D, with_phi, scs);
+    if (tid < 64) combine_stats(D, with_phi, scs);
     __syncthreads();
-    if (xb.item == 0 && threadIdx.x < SC_COUNT) glb(D.scal)[threadIdx.x] = scs[threadIdx.x];
+    if (item == 0 && tid < SC_COUNT) glb(D.scal)[tid] = scs[tid];
 #pragma unroll
     for (int q = 0; q < SC_COUNT; ++q) sc[q] = scs[q];
   } else {
@@ -605,6 +616,17 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   for (int i = 0; i < E; ++i) out[last_pos<N, +1>(i, t)] = v[i];
 }
 
+template <int N, int LPW>
+__global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const* dptrs, const float2* __restrict__ tw,
+                                                             int k, int use_plane, int fin, int with_phi) {
+  __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
+  __shared__ float2 s_tw[N];
+  __shared__ float scs[SC_COUNT];
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
+  row1_body<N, LPW, true>(D, D.y, D.cur, xb.item, tw, k, use_plane, fin, with_phi, lds, s_tw, scs, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_col: column strip of W columns.  Inverse 1-D DFT down each column and the
 // 1/N scale give b = A_phi^H yhat; then per pixel the Eq. (3) initialisation
@@ -612,20 +634,18 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 // and the forward 1-D DFT of mu down the column (unnormalised) -> U.
 // grid (N/W, streams), block W * N/E
 // ---------------------------------------------------------------------------
-template <int N, int W>
-__global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                          int k, int do_rinit, int mat) {
+// Body of one column-pass block (item = W columns) of one stream with
+// current state buffer cur; lds holds N * ColLds<W>::STRIDE entries.
+template <int N, int W, bool STAGE_TW>
+__device__ __forceinline__ void col_body(const StreamDesc& D, int cur, int item, const float2* __restrict__ tw, int k,
+                                         int do_rinit, int mat, float2* lds, float2* s_tw, int tid) {
   constexpr int E = Plan<N>::E;
-  __shared__ float2 lds[N * ColLds<W>::STRIDE];
-  __shared__ float2 s_tw[N];
-  const XcdBlock xb = xcd_block();
-  const auto& D = desc_ref(dptrs[xb.strm]);
-  const int w = threadIdx.x % W, t = threadIdx.x / W;
-  const int col = xb.item * W + w;
+  const int w = tid % W, t = tid / W;
+  const int col = item * W + w;
   float2 v[E];
   float rpv[E];
-  const float* rin = glb(D.r[(D.cur + k) & 1]);
-  float* rmat = glb(D.r[((D.cur + k) & 1) ^ 1]);
+  const float* rin = glb(D.r[(cur + k) & 1]);
+  float* rmat = glb(D.r[((cur + k) & 1) ^ 1]);
   // output pointers and constants are read before any store (see k_stats)
   float* bbo = glb(D.bb);
   float2* uo = glb(D.U);
@@ -635,7 +655,8 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
   for (int i = 0; i < E; ++i) v[i] = glb(D.T)[first_pos<N, +1>(i, t) * N + col];
 #pragma unroll
   for (int i = 0; i < E; ++i) rpv[i] = rin[last_pos<N, +1>(i, t) * N + col];
-  for (int i = threadIdx.x; i < N; i += W * (N / E)) s_tw[i] = tw[i];
+  if (STAGE_TW)
+    for (int i = tid; i < N; i += W * (N / E)) s_tw[i] = tw[i];
   if (glb(D.scal)[SC_FLAG] != 0.0f) return;
   ColLds<W> L{lds + w};
   line_fft<N, +1>(v, t, L, s_tw);
@@ -649,13 +670,23 @@ __global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* d
     const float ri = do_rinit ? rinit_of(rp, bb, lam, alpha, fl) : rp;
     const float wgt = wiener_of(ri, s2);
     bbo[n * N + col] = bb;
-    if (mat) rmat[n * N + col] = ri;  // the colour passes update this copy in place
+    if (mat) rmat[n * N + col] = ri;  // the whole-image colour passes update this copy in place
     v[i] = cscale(b, wgt);
   }
   __syncthreads();
   line_fft<N, -1>(v, t, L, s_tw);
 #pragma unroll
   for (int i = 0; i < E; ++i) uo[last_pos<N, -1>(i, t) * N + col] = v[i];
+}
+
+template <int N, int W>
+__global__ __launch_bounds__(W*(N / Plan<N>::E)) void k_col(StreamDesc* const* dptrs, const float2* __restrict__ tw,
+                                                          int k, int do_rinit, int mat) {
+  __shared__ float2 lds[N * ColLds<W>::STRIDE];
+  __shared__ float2 s_tw[N];
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
+  col_body<N, W, true>(D, D.cur, xb.item, tw, k, do_rinit, mat, lds, s_tw, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,27 +722,27 @@ __device__ __forceinline__ float fatan2(float y, float x) {
 // x0 = wrap(phi' - theta) by (kappa/2)(phi - theta~)^2 with kappa = c sinc(x0),
 // theta~ = phi' - x0.  Writes (kappa, theta~) into T (zero off the pupil).
 // ---------------------------------------------------------------------------
-template <int N, int LPW>
-__global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const* dptrs, const float2* __restrict__ tw,
-                                                             int k, int use_plane, int mat) {
+// Body of one row2 block (item = LPW rows) of one stream with frame yf and
+// current state buffer cur.
+template <int N, int LPW, bool STAGE_TW>
+__device__ __forceinline__ void row2_body(const StreamDesc& D, const float2* yf, int cur, int item,
+                                          const float2* __restrict__ tw, int k, int use_plane, int mat, float2* lds,
+                                          float2* s_tw, int tid) {
   constexpr int E = Plan<N>::E, T = N / E;
-  __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
-  __shared__ float2 s_tw[N];
-  const XcdBlock xb = xcd_block();
-  const auto& D = desc_ref(dptrs[xb.strm]);
   const float* sc = glb(D.scal);
-  const int line = threadIdx.x / T, t = threadIdx.x - line * T;
-  const int row = xb.item * LPW + line;
-  for (int i = threadIdx.x; i < N; i += LPW * T) s_tw[i] = tw[i];
+  const int line = tid / T, t = tid - line * T;
+  const int row = item * LPW + line;
+  if (STAGE_TW)
+    for (int i = tid; i < N; i += LPW * T) s_tw[i] = tw[i];
   float2 v[E];
   const float2* u = glb(D.U) + row * N;
-  const float* phi = glb(D.phi[(D.cur + k) & 1]) + row * N;
-  const float2* y = glb(D.y) + row * N;
+  const float* phi = glb(D.phi[(cur + k) & 1]) + row * N;
+  const float2* y = glb(yf) + row * N;
   // descriptor fields are read before any store (see k_stats)
   const auto geo = glb(D.geo) + row * N;
   const float c2s = 2.0f / D.sigma2;
   float2* out = glb(D.T) + row * N;
-  float* pmat = glb(D.phi[((D.cur + k) & 1) ^ 1]) + row * N;
+  float* pmat = glb(D.phi[((cur + k) & 1) ^ 1]) + row * N;
   // every global read is issued up front: the aperture bytes at this
   // thread's output positions (first: the loads below wait for them), the
   // row, and y and phi at the output positions that lie in the pupil
@@ -761,6 +792,167 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
       if (mat) pmat[m] = p;  // the colour passes update this copy in place
     }
     out[m] = res;
+  }
+}
+
+template <int N, int LPW>
+__global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const* dptrs, const float2* __restrict__ tw,
+                                                             int k, int use_plane, int mat) {
+  __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
+  __shared__ float2 s_tw[N];
+  const XcdBlock xb = xcd_block();
+  const auto& D = desc_ref(dptrs[xb.strm]);
+  row2_body<N, LPW, true>(D, D.y, D.cur, xb.item, tw, k, use_plane, mat, lds, s_tw, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// k_frame: the stats, row1, column and row2 stages of `count` streams of one
+// N as one persistent work list.  Each workgroup repeatedly claims the next
+// ticket of its XCD's queue and runs that item with the same block body as
+// the eager kernel of its stage, so every result is bit for bit the eager
+// path's.
+//
+// Work list.  Stream s is dealt to queue s % nq.  A queue's tickets form
+// slots of SLOT = nA + nB + nC + nD items: at slot j the stats items of the
+// queue's stream j, the row1 items of its stream j - lag, the column items of
+// j - 2 lag and the row2 items of j - 3 lag (items of streams out of range
+// are empty; without a stats stage, k > 0, the other stages move up one
+// place).  An item waits until every item of the previous stage of its stream
+// has completed; those carry smaller tickets of the same queue and have been
+// claimed before it, so each wait is on work that is already running or
+// done: the list cannot deadlock.  Waits are bounded by spin_limit polls; a
+// wait that gives up sets the stream's give-up word and the item runs anyway,
+// so every workgroup ends (giveup != 0 forces this, for tests).
+//
+// Coherence.  A workgroup claims from the queue of the XCD it runs on (the
+// hardware XCC_ID register), so every item of a stream runs on one XCD,
+// whose L2 all its CUs share.  A producer's stores have completed (vmcnt(0))
+// before its completion counter is incremented at L2, and a consumer first
+// touches the produced data (through L1 and L2) after it has read the counter
+// there; within a launch each produced array is read only after it is
+// written.  Frame arguments reach every stage from the kernel arguments, so
+// no stage reads a descriptor field that this launch writes.
+//
+// The last workgroup to finish resets the queue tickets, and the last row2
+// item of a stream its stage counters, so the next launch starts from zero.
+// grid: persistent, a multiple of nq; block 256 (LPW, W chosen so that each
+// stage's block is 256 threads).
+// ---------------------------------------------------------------------------
+template <int N>
+struct FrameTiles {  // rows per row item and columns per column item at 256 threads
+  static constexpr int T = N / Plan<N>::E;
+  static constexpr int LPW = 256 / T, W = 256 / T;
+  static constexpr int ROWL = LPW * RowLds<N>::STRIDE, COLL = N * ColLds<W>::STRIDE;
+  static constexpr int LDS = ROWL > COLL ? ROWL : COLL;
+};
+
+__device__ __forceinline__ unsigned xcc_id() {
+  // hwreg(HW_REG_XCC_ID, 0, 4): the XCD the wave runs on
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+}
+__device__ __forceinline__ unsigned ctl_load(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_frame(StreamDesc** dptrs, int count, FrameArgs a, int use_args,
+                                               const float2* __restrict__ tw, int k, int mode, unsigned* ctl0,
+                                               int nq, int lag, unsigned spin_limit, int giveup, int mat) {
+  using FT = FrameTiles<N>;
+  constexpr int LPW = FT::LPW, W = FT::W;
+  __shared__ float2 lds[FT::LDS];
+  __shared__ float2 s_tw[N];
+  __shared__ float red[6 * 16];
+  __shared__ float scs[SC_COUNT];
+  __shared__ int s_ticket;
+  const int fin = k == 0, first = (mode && k == 0) ? 1 : 0;
+  const int nA = fin ? (N * N) / STATS_PIX_PER_BLOCK : 0, nB = N / LPW, nC = N / W, nD = N / LPW;
+  const int SLOT = nA + nB + nC + nD;
+  const int s0 = fin ? 0 : 1;  // first stage present
+  const int q = (int)(xcc_id() % (unsigned)nq);
+  const int Sq = q < count ? (count - q + nq - 1) / nq : 0;
+  const int tickets = Sq > 0 ? (Sq + (3 - s0) * lag) * SLOT : 0;
+  const int need[4] = {nA, nB, nC, nD};
+  for (int i = threadIdx.x; i < N; i += 256) s_tw[i] = tw[i];
+  for (;;) {
+    __syncthreads();  // the previous item is done with the LDS (and s_ticket)
+    if (threadIdx.x == 0) s_ticket = (int)atomicAdd(ctl0 + CTL_TICKETS + q, 1u);
+    __syncthreads();
+    const int t = s_ticket;
+    if (t >= tickets) break;
+    const int slot = t / SLOT, pos = t - slot * SLOT;
+    int stage, item;
+    if (pos < nA) {
+      stage = 0;
+      item = pos;
+    } else if (pos < nA + nB) {
+      stage = 1;
+      item = pos - nA;
+    } else if (pos < nA + nB + nC) {
+      stage = 2;
+      item = pos - nA - nB;
+    } else {
+      stage = 3;
+      item = pos - nA - nB - nC;
+    }
+    const int j = slot - (stage - s0) * lag;
+    if (j < 0 || j >= Sq) continue;  // empty item
+    // the thread index, opaque to the compiler in each item: otherwise every
+    // stage's per-thread index arithmetic is hoisted out of the loop and all
+    // of it stays live at once
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int strm = j * nq + q;
+    StreamDesc* const dp = use_args == 2 ? a.d[strm] : dptrs[strm];
+    const auto& D = desc_ref(dp);
+    const float2* y = use_args ? a.y[strm] : D.y;
+    const int cur = use_args ? a.cur[strm] : D.cur;
+    unsigned* ctl = D.ctl;
+    // ---- wait for the previous stage of this stream
+    if (stage > s0) {
+      if (threadIdx.x == 0) {
+        unsigned polls = 0;
+        while (giveup || ctl_load(ctl + CTL_STAGE + stage - 1) < (unsigned)need[stage - 1]) {
+          if (giveup || ++polls > spin_limit) {
+            __hip_atomic_store(ctl + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+    }
+    // ---- the item (block bodies of the eager kernels)
+    if (stage == 0) {
+      stats_body<N>(D, y, cur, item, mode, red, tid);
+      if (use_args && item == 0 && threadIdx.x == 0) {
+        // the later launches of the frame (M-step, diagnostics) read these
+        const auto d = glb(dp);
+        d->y = y;
+        d->cur = cur;
+        if (use_args == 2) glb(dptrs)[strm] = dp;
+      }
+    } else if (stage == 1) {
+      row1_body<N, LPW, false>(D, y, cur, item, tw, k, first, fin, mode, lds, s_tw, scs, tid);
+    } else if (stage == 2) {
+      col_body<N, W, false>(D, cur, item, tw, k, first, mat, lds, s_tw, tid);
+    } else {
+      row2_body<N, LPW, false>(D, y, cur, item, tw, k, first, mat, lds, s_tw, tid);
+    }
+    // ---- completion: every store of the item has reached L2 first
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned done = atomicAdd(ctl + CTL_STAGE + stage, 1u);
+      if (stage == 3 && done + 1 == (unsigned)nD) {
+        for (int g = 0; g < 4; ++g) __hip_atomic_store(ctl + CTL_STAGE + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  if (threadIdx.x == 0 && atomicAdd(ctl0 + CTL_FINISHED, 1u) + 1 == gridDim.x) {
+    for (int g = 0; g < CTL_MAX_QUEUES; ++g)
+      __hip_atomic_store(ctl0 + CTL_TICKETS + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctl0 + CTL_FINISHED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -960,9 +1152,10 @@ struct MsGeom {
 // tile.  The tile and a 4-pixel halo of r and phi are staged in LDS; pass c
 // updates the colour-c pixels of the region shrunk by c+1, so the inner tile
 // sees exactly the values a whole-grid sweep produces.  All global reads of
-// a block are issued before the first wait.  s = E|g|^2 is computed once per
-// staged pixel; each thread keeps the per-pixel constants of the pixels it
-// updates (LDS offset, border mask, s, pupil-neighbour weight, kappa, theta~)
+// a block are issued before the first wait.  r is staged after the Eq. (3)
+// initialisation; s = E|g|^2 is formed only at the pixels a thread updates
+// (no neighbour needs it); each thread keeps the per-pixel constants of those
+// pixels (LDS offset, border mask, s, pupil-neighbour weight, kappa, theta~)
 // in registers.  Colour(i, j) = (i mod 2) + 2 (j mod 2).  Reads state buffer
 // in = (cur + k) & 1, writes in ^ 1.  grid (tiles, streams), block BT (the
 // first pass's pixel count rounded up to whole waves); blocks are remapped
@@ -971,14 +1164,14 @@ struct MsGeom {
 // ---------------------------------------------------------------------------
 template <int N, int TH, int TW>
 __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mstep(StreamDesc* const* dptrs, int k, int use_plane,
-                                                              int do_rinit) {
+                                                                                                        int do_rinit) {
   using G = MsGeom<TH, TW>;
   constexpr int BT = G::BT;
   constexpr int RW = G::RW, RP = G::RP, SLOTS = G::SLOTS;
   constexpr int TPC = N / TW, TPR = N / TH;
   constexpr int TILES = TPC * TPR;
   constexpr int offs[8] = {-RW, RW, -1, 1, -RW - 1, -RW + 1, RW - 1, RW + 1};
-  __shared__ __align__(16) float sR[RP], sP[RP], sS[RP];
+  __shared__ __align__(16) float sR[RP], sP[RP];
   const int total = TILES * gridDim.y;
   const int L = blockIdx.x + blockIdx.y * TILES;
   const int logical = (total % 8 == 0) ? (L % 8) * (total / 8) + (L / 8) : L;
@@ -994,45 +1187,57 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const float* sc = glb(D.scal);
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
   // ---- every global read is issued up front: r, |b|^2 and phi of the
-  // region in 4-pixel vectors (the halo is 4 wide and tile origins are
-  // multiples of 4, so a vector is wholly on or off the grid), and
-  // (kappa, theta~) of the pupil pixels this thread updates.  phi is zero off
-  // the pupil in every state buffer, so it is read unconditionally.
+  // region in 4-pixel vectors with their aperture bytes (the halo is 4 wide
+  // and tile origins are multiples of 4, so a vector is wholly on or off the
+  // grid), and |b|^2 and (kappa, theta~) of the pixels this thread updates.
+  // phi is zero off the pupil in every state buffer, so it is read
+  // unconditionally.  Tiles away from the grid border have every neighbour
+  // and read their whole region without bounds tests.
   constexpr int RW4 = RW / 4, RP4 = G::RH * RW4;
   constexpr int SR = (RP4 + BT - 1) / BT;
   const float4* rin4 = reinterpret_cast<const float4*>(rin);
   const float4* pin4 = reinterpret_cast<const float4*>(pin);
   const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
   const auto ktp = glb(D.T);
+  const auto bbp = glb(D.bb);
   const auto geop = glb(D.geo);
   const auto geo4 = reinterpret_cast<gptr<const unsigned>>(geop);
+  const bool border = ti == 0 || ti == TPR - 1 || tj == 0 || tj == TPC - 1;
   float4 gr[SR], gb[SR], gph[SR];
   unsigned gw[SR];  // aperture bytes of the 4 pixels of the vector
+  auto load_region = [&](auto brd) {
+    constexpr bool BRD = decltype(brd)::value;
 #pragma unroll
-  for (int q = 0; q < SR; ++q) {
-    const int idx = threadIdx.x + q * BT;
-    const int li = idx / RW4, gi = gi0 + li, gj = gj0 + 4 * (idx - li * RW4);
-    gr[q] = gb[q] = gph[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    gw[q] = 0u;
-    if (idx < RP4 && gi >= 0 && gi < N && gj >= 0 && gj < N) {
-      const int v = (gi * N + gj) / 4;
-      gr[q] = rin4[v];
-      gb[q] = bb4[v];
-      gph[q] = pin4[v];
-      gw[q] = geo4[v];
+    for (int q = 0; q < SR; ++q) {
+      const int idx = threadIdx.x + q * BT;
+      const int li = idx / RW4, gi = gi0 + li, gj = gj0 + 4 * (idx - li * RW4);
+      // every thread of a round that ends inside the region has a vector
+      const bool in_region = (q + 1) * BT <= RP4 || idx < RP4;
+      if (in_region && (!BRD || (gi >= 0 && gi < N && gj >= 0 && gj < N))) {
+        const unsigned v = (unsigned)(gi * N + gj) / 4u;
+        gr[q] = rin4[v];
+        gb[q] = bb4[v];
+        gph[q] = pin4[v];
+        gw[q] = geo4[v];
+      } else {
+        gr[q] = gb[q] = gph[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        gw[q] = 0u;
+      }
     }
-  }
+  };
+  if (border)
+    load_region(std::true_type{});
+  else
+    load_region(std::false_type{});
   // per own pixel, one packed word: LDS offset (bits 0-15), neighbour mask
   // (16-19), pupil-neighbour weight in twelfths (20-23), in-pupil flag (24);
-  // -1 when the pixel is off the grid or beyond this pass.  Then kappa and
-  // theta~.  Tiles away from the grid border have every neighbour.  The
-  // pupil bits come from the stream's per-pixel geometry bytes, and (kappa,
-  // theta~) is read at every own pixel ((0, 0) off the pupil); both loads are
-  // unconditional (a slot without a pixel reads pixel 0) and the bytes are
-  // merged once every load has arrived.
-  const bool border = ti == 0 || ti == TPR - 1 || tj == 0 || tj == TPC - 1;
+  // -1 when the pixel is off the grid or beyond this pass.  Then |b|^2, kappa
+  // and theta~.  The pupil bits come from the stream's per-pixel geometry bytes,
+  // and (kappa, theta~) is read at every own pixel ((0, 0) off the pupil);
+  // the loads are unconditional (a slot without a pixel reads pixel 0) and
+  // the bytes are merged once every load has arrived.
   int opk[SLOTS], ogeo[SLOTS];
-  float okap[SLOTS], ott[SLOTS];
+  float okap[SLOTS], ott[SLOTS], os[SLOTS];
   static_for<0, 4>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
 #pragma unroll
@@ -1043,10 +1248,11 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
       const int li = G::li0(c) + 2 * u, lj = G::lj0(c) + 2 * (idx - u * G::nv(c));
       const int gi = gi0 + li, gj = gj0 + lj;
       const bool own = idx < G::n(c) && (!border || (gi >= 0 && gi < N && gj >= 0 && gj < N));
-      const int gp = own ? gi * N + gj : 0;
+      const unsigned gp = own ? (unsigned)(gi * N + gj) : 0u;
       const float2 kt = ktp[gp];
       okap[slot] = kt.x;
       ott[slot] = kt.y;
+      os[slot] = bbp[gp];  // |b|^2 here; s = E|g|^2 once r is staged
       ogeo[slot] = geop[gp];
       opk[slot] = own ? (li * RW + lj) | ((border ? nb_mask(gi, gj, N) : NB_ALL) << 16) : -1;
     }
@@ -1061,38 +1267,36 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
     return;
   }
   const float c0 = sc[SC_C0], c1 = sc[SC_C1], c2 = sc[SC_C2];
-  // ---- stage the region: r after the Eq. (3) initialisation, s = E|g|^2,
-  // and phi' (zero off the pupil and off the grid)
+  // ---- stage the region: r after the Eq. (3) initialisation and phi' (phi
+  // less the tip/tilt plane on the pupil; zero off the pupil and off the grid)
 #pragma unroll
   for (int q = 0; q < SR; ++q) {
     const int idx = threadIdx.x + q * BT;
     if (idx < RP4) {
       const int li = idx / RW4, c4 = idx - li * RW4;
       const int gi = gi0 + li, gj = gj0 + 4 * c4;
-      float r[4] = {0.f, 0.f, 0.f, 0.f}, sv[4] = {0.f, 0.f, 0.f, 0.f}, p[4] = {0.f, 0.f, 0.f, 0.f};
-      if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
-        const float rv[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
-        const float bv[4] = {gb[q].x, gb[q].y, gb[q].z, gb[q].w};
-        const float pv[4] = {gph[q].x, gph[q].y, gph[q].z, gph[q].w};
+      const float rv[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
+      const float bv[4] = {gb[q].x, gb[q].y, gb[q].z, gb[q].w};
+      const float pv[4] = {gph[q].x, gph[q].y, gph[q].z, gph[q].w};
+      float r[4], p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          r[e] = do_rinit ? rinit_of(rv[e], bv[e], lam, alpha, fl) : rv[e];
-          sv[e] = second_moment(wiener_of(r[e], s2), bv[e], s2);
-          if (geo_in(gw[q] >> (8 * e))) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
-        }
+      for (int e = 0; e < 4; ++e) {
+        // off the grid r stays 0 (rv = bv = 0; the weight of such a neighbour is 0)
+        r[e] = do_rinit ? rinit_of(rv[e], bv[e], lam, alpha, fl) : rv[e];
+        if (geo_in(gw[q] >> (8 * e))) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
       }
+      if (border && !(gi >= 0 && gi < N && gj >= 0 && gj < N)) r[0] = r[1] = r[2] = r[3] = 0.f;
       const int o4 = li * RW4 + c4;
       reinterpret_cast<float4*>(sR)[o4] = make_float4(r[0], r[1], r[2], r[3]);
-      reinterpret_cast<float4*>(sS)[o4] = make_float4(sv[0], sv[1], sv[2], sv[3]);
       reinterpret_cast<float4*>(sP)[o4] = make_float4(p[0], p[1], p[2], p[3]);
     }
   }
   __syncthreads();
-  float os[SLOTS];
+  // s = E|g|^2 of the pixels this thread updates, from their staged r
 #pragma unroll
   for (int slot = 0; slot < SLOTS; ++slot) {
     opk[slot] = opk[slot] >= 0 ? opk[slot] | ((ogeo[slot] & 31) << 20) : -1;
-    os[slot] = opk[slot] >= 0 ? sS[opk[slot] & 0xffff] : 0.f;
+    os[slot] = opk[slot] >= 0 ? second_moment(wiener_of(sR[opk[slot] & 0xffff], s2), os[slot], s2) : 0.f;
   }
   const float inv_sp = D.qg_inv_sp, lc = D.qg_lc, pmq = D.qg_pmq, qop = D.qg_qop;
   // ---- the four colour passes (same-colour pixels are never neighbours, so
@@ -1572,8 +1776,7 @@ static hipError_t mstep_n(StreamDesc* const* d, int count, int k, int use_plane,
   if (th == TH && tw == TW) {                                                                                  \
     if constexpr (N % TH == 0 && N % TW == 0) {                                                                \
       hipLaunchKernelGGL((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3((MsGeom<TH, TW>::BT)), 0, st, \
-                         d, k,                                                                                 \
-                         use_plane, do_rinit);                                                                 \
+                         d, k, use_plane, do_rinit);                                                           \
       return hipGetLastError();                                                                                \
     }                                                                                                          \
   }
@@ -1617,6 +1820,46 @@ hipError_t launch_mstep(StreamDesc* const* d, int count, int N, int k, int use_p
 #define DDH_X(NN) return mstep_n<NN>(d, count, k, use_plane, do_rinit, tc.m_tile_h, tc.m_tile_w, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
+}
+
+hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int mode,
+                        const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned* ctl0, int nq,
+                        int lag, unsigned spin_limit, int giveup, int whole_image, hipStream_t st) {
+  if (nq < 1 || nq > CTL_MAX_QUEUES || lag < 1) return hipErrorInvalidValue;
+  StreamDesc** list = const_cast<StreamDesc**>(dptrs);
+  // persistent grid: 3 workgroups of 256 threads per CU (the column stage's
+  // registers allow 3 waves per SIMD), a multiple of nq, no more than items
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
+    FrameArgs a{};
+    const int n = count - off < FRAME_ARGS_MAX ? count - off : FRAME_ARGS_MAX;
+    if (ys)
+      for (int i = 0; i < n; ++i) {
+        a.y[i] = ys[off + i];
+        a.cur[i] = curs[off + i];
+        a.d[i] = ds ? ds[off + i] : nullptr;
+      }
+    const int use_args = ys ? (ds ? 2 : 1) : 0;
+    const int per_stream = 4 * N;  // upper bound of the items of one stream
+    int grid = 3 * cus;
+    if (grid > n * per_stream) grid = n * per_stream;
+    grid = ((grid + nq - 1) / nq) * nq;
+    unsigned* c0 = ctl0;
+#define DDH_F(NN)                                                                                           \
+  hipLaunchKernelGGL(k_frame<NN>, dim3(grid), dim3(256), 0, st, list + off, n, a, use_args, tw, k, mode, c0, nq, \
+                     lag, spin_limit, giveup, whole_image);                                                   \
+  break;
+    switch (N) {
+      case 64: DDH_F(64)
+      case 128: DDH_F(128)
+      case 256: DDH_F(256)
+      case 512: DDH_F(512)
+      default: return hipErrorInvalidValue;
+    }
+#undef DDH_F
+  }
+  return hipGetLastError();
 }
 
 template <int N>

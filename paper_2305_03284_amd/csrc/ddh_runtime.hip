@@ -228,7 +228,25 @@ TileConfig tiles_for(int N) {
   return it == tile_cache().end() ? default_tiles(N) : it->second;
 }
 
-const char* kKindNames[KK_COUNT] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "begin"};
+const char* kKindNames[KK_COUNT] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "begin",
+                                    "frame_worklist"};
+
+// XCDs of a device (queues of the work-list kernel), cached per device.
+int xcd_count(int dev) {
+  static std::mutex mu;
+  static int cache[kMaxDev] = {0};
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0 || dev >= kMaxDev) return 1;
+  if (!cache[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || n < 1) {
+      (void)hipGetLastError();
+      n = 1;
+    }
+    cache[dev] = std::min(n, (int)CTL_MAX_QUEUES);
+  }
+  return cache[dev];
+}
 
 }  // namespace
 
@@ -269,6 +287,15 @@ struct Group {
   int count;
   TileConfig tc;
   const float2* tw;
+  unsigned* ctl0 = nullptr;  // work-list control words of the group's launch (its first stream's)
+};
+
+// Work-list (persistent frame kernel) settings of a batch.
+struct Worklist {
+  int nq = 1;                   // XCD queues
+  int lag = 2;                  // slots between consecutive stages of a stream
+  unsigned spin = 1u << 20;     // polls before a wait gives up
+  int giveup = 0;               // failure-path test: every wait gives up at once
 };
 
 // A lane is a subset of a batch's streams whose launch chain runs on its own
@@ -294,6 +321,8 @@ struct ddh_batch_s {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool capturing = false;             // enqueueing into the graph capture (frame start from descriptors)
+  bool worklist = false;              // DDH_BATCH_WORKLIST: persistent frame kernel
+  Worklist wl;
   std::vector<const float2*> yord;
   std::vector<int> curord;       // host parity of each stream, in descriptor order
   // timing
@@ -381,6 +410,37 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
   }
   (void)total;
   return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around);
+}
+
+// One frame on the work-list path: per EM iteration one persistent launch
+// per group (stats at k = 0, row1, column and row2 as one work list), then
+// the groups' M-steps.  Frame start from ys/curs/ds at k = 0 (nullptr: from
+// the descriptors); later iterations read it from the descriptors.
+template <class OnLaunch>
+int enqueue_frame_worklist(StreamDesc** dptrs, const Group* groups, int ngroups, int n_k, int mode, hipStream_t st,
+                           OnLaunch&& around, const Worklist& wl, const float2* const* ys = nullptr,
+                           const int* curs = nullptr, StreamDesc* const* ds = nullptr) {
+  hipError_t e;
+  const int iters = mode ? n_k : 1;
+  for (int k = 0; k < iters; ++k) {
+    const int first = (mode && k == 0) ? 1 : 0;
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      const bool args = k == 0 && ys != nullptr;
+      e = around(KK_FRAME, [&] {
+        return launch_frame(dptrs + g.off, g.count, g.N, g.tw, k, mode, args ? ys + g.off : nullptr,
+                            args ? curs + g.off : nullptr, args && ds ? ds + g.off : nullptr, g.ctl0, wl.nq, wl.lag,
+                            wl.spin, wl.giveup, g.tc.m_tile_h == 0, st);
+      });
+      if (e != hipSuccess) return hip_fail(e, "launch_frame");
+    }
+    for (int q = 0; q < ngroups; ++q) {
+      const Group& g = groups[q];
+      e = around(KK_MSTEP, [&] { return launch_mstep(dptrs + g.off, g.count, g.N, k, first, first, g.tc, st); });
+      if (e != hipSuccess) return hip_fail(e, "launch_mstep");
+    }
+  }
+  return DDH_OK;
 }
 
 struct NoTiming {
@@ -475,7 +535,7 @@ int ddh_default_params(int N, ddh_params* p) {
 
 // Device allocation of one stream (one hipMalloc): offsets of its buffers.
 struct StreamLayout {
-  size_t r0, r1, p0, p1, T, U, bb, part, scal, desc, dptr, diag, geo, total;
+  size_t r0, r1, p0, p1, T, U, bb, part, scal, ctl, desc, dptr, diag, geo, total;
   explicit StreamLayout(int N) {
     const size_t px = (size_t)N * N;
     const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
@@ -494,6 +554,7 @@ struct StreamLayout {
     bb = take(px * 4);
     part = take((size_t)nb * PART_STRIDE * 4);
     scal = take(SC_COUNT * 4);
+    ctl = take(CTL_WORDS * 4);  // zeroed with the scratch at creation
     desc = take(sizeof(StreamDesc));
     dptr = take(sizeof(StreamDesc*));
     diag = take(kDiagParts * 3 * sizeof(double) + 64);
@@ -629,6 +690,7 @@ int ddh_init_stream(const ddh_params* p, const float* aperture, void* hip_stream
   h.bb = (float*)(mem + o_bb);
   h.part = (float*)(mem + o_part);
   h.scal = (float*)(mem + o_scal);
+  h.ctl = (unsigned*)(mem + lay.ctl);
   h.geo = geo;
   h.N = N;
   h.cur = 0;
@@ -776,6 +838,7 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
   const size_t bytes = sizeof(float) * (size_t)s->N * s->N;
   DDH_CHECK(hipMemcpyAsync(s->h.r[s->parity], r, bytes, hipMemcpyDeviceToDevice, st));
   DDH_CHECK(launch_copy_pupil(s->h.phi[s->parity], phi, s->N, s->h.geo, st));
+  DDH_CHECK(launch_fill_zero(reinterpret_cast<float*>(s->h.ctl), CTL_WORDS, st));  // work-list words
   s->n = n;
   return DDH_OK;
 }
@@ -783,10 +846,21 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
 int ddh_status(ddh_stream_t s, void* hip_stream) {
   int rc = check_stream(s);
   if (rc != DDH_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   float flag = 0.f;
-  DDH_CHECK(hipMemcpyAsync(&flag, s->h.scal + SC_FLAG, sizeof(float), hipMemcpyDeviceToHost,
-                           static_cast<hipStream_t>(hip_stream)));
-  DDH_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  unsigned gave_up = 0;
+  DDH_CHECK(hipMemcpyAsync(&flag, s->h.scal + SC_FLAG, sizeof(float), hipMemcpyDeviceToHost, st));
+  DDH_CHECK(hipMemcpyAsync(&gave_up, s->h.ctl + CTL_GIVEUP, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  DDH_CHECK(hipStreamSynchronize(st));
+  if (gave_up) {
+    // reported once.  After a give-up an item of an earlier stage can finish
+    // after its stream's counters were reset, so all the stream's work-list
+    // words are cleared (every launch on st has ended by now)
+    DDH_CHECK(launch_fill_zero(reinterpret_cast<float*>(s->h.ctl), CTL_WORDS, st));
+    DDH_CHECK(hipStreamSynchronize(st));
+    g_last_err = "a wait of the work-list frame kernel gave up; the stream's state is unspecified";
+    return DDH_EDEVICE;
+  }
   return flag != 0.f ? DDH_EDATA : DDH_OK;
 }
 
@@ -862,7 +936,11 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
 }
 
 // ----------------------------------------------------------------- batches
-int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out) {
+// Batch creation; `over` (may be null) gives the tilings to use instead of
+// the process-wide ones (the autotuners time candidates this way without
+// installing them).
+static int batch_create_impl(const ddh_stream_t* streams, int count, int flags,
+                             const std::map<int, TileConfig>* over, ddh_batch_t* out) {
   if (!streams || count <= 0 || !out) return DDH_EINVAL;
   int dev = -1, n_k = -1;
   for (int i = 0; i < count; ++i) {
@@ -910,9 +988,12 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
     Lane& ln = b->lanes[l];
     ln.off = (int)order.size();
     for (int N : {64, 128, 256, 512}) {
-      Group g{N, (int)order.size(), 0, tiles_for(N), nullptr};
+      TileConfig tc = tiles_for(N);
+      if (over && over->count(N)) tc = over->at(N);
+      Group g{N, (int)order.size(), 0, tc, nullptr};
       for (int i : members[l]) {
         if (streams[i]->N != N) continue;
+        if (g.count == 0) g.ctl0 = streams[i]->h.ctl;
         b->pos[i] = (int)order.size();
         order.push_back(streams[i]->d);
         g.count++;
@@ -927,6 +1008,9 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
   }
   b->yord.assign(count, nullptr);
   b->curord.assign(count, 0);
+  b->worklist = (flags & DDH_BATCH_WORKLIST) != 0;
+  b->wl.nq = xcd_count(dev);
+  b->wl.giveup = (flags & DDH_BATCH_TEST_GIVEUP) ? 1 : 0;
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
   if (e != hipSuccess) {
     delete b;
@@ -955,12 +1039,25 @@ int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batc
   return DDH_OK;
 }
 
-int ddh_batch_destroy(ddh_batch_t b) {
+int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out) {
+  return batch_create_impl(streams, count, flags, nullptr, out);
+}
+
+// Release a batch; with device_sync == false only the batch's own HIP
+// streams are waited for (the caller has synchronised the stream it stepped
+// the batch on), so other work on the device is not stalled.
+static int batch_release(ddh_batch_t b, bool device_sync) {
   if (!b) return DDH_EINVAL;
   if (!is_live(b)) return DDH_ESTATE;
   live_remove(b);
   set_device_of(b->device);
-  (void)hipDeviceSynchronize();
+  if (device_sync) {
+    (void)hipDeviceSynchronize();
+  } else {
+    for (Lane& ln : b->lanes)
+      if (ln.s) (void)hipStreamSynchronize(ln.s);
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+  }
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (Lane& ln : b->lanes) {
@@ -973,6 +1070,8 @@ int ddh_batch_destroy(ddh_batch_t b) {
   delete b;
   return DDH_OK;
 }
+
+int ddh_batch_destroy(ddh_batch_t b) { return batch_release(b, true); }
 
 int ddh_batch_set_timing(ddh_batch_t b, int enable) {
   if (!b) return DDH_EINVAL;
@@ -1011,14 +1110,24 @@ static int drain_timing(ddh_batch_t b) {
 
 // Fork the lanes off stream st, enqueue each lane's chain on its own stream,
 // join them back into st (capturable: the graph then has parallel branches).
+extern "C++" {
+template <class OnLaunch>
+static int batch_enqueue(ddh_batch_t b, const std::vector<Group>& groups, int count, hipStream_t st, OnLaunch&& around,
+                         const float2* const* ys, const int* cs) {
+  if (b->worklist)
+    return enqueue_frame_worklist(b->dptrs, groups.data(), (int)groups.size(), b->n_k, 1, st, around, b->wl, ys, cs);
+  return enqueue_frame(b->dptrs, groups, count, b->n_k, 1, st, around, ys, cs);
+}
+}  // extern "C++"
+
 static int enqueue_lanes(ddh_batch_t b, hipStream_t st) {
   const float2* const* ys = b->capturing ? nullptr : b->yord.data();
   const int* cs = b->curord.data();
-  if (b->lanes.size() == 1) return enqueue_frame(b->dptrs, b->lanes[0].groups, b->lanes[0].count, b->n_k, 1, st, NoTiming{}, ys, cs);
+  if (b->lanes.size() == 1) return batch_enqueue(b, b->lanes[0].groups, b->lanes[0].count, st, NoTiming{}, ys, cs);
   DDH_CHECK(hipEventRecord(b->fork, st));
   for (Lane& ln : b->lanes) {
     DDH_CHECK(hipStreamWaitEvent(ln.s, b->fork, 0));
-    int rc = enqueue_frame(b->dptrs, ln.groups, ln.count, b->n_k, 1, ln.s, NoTiming{}, ys, cs);
+    int rc = batch_enqueue(b, ln.groups, ln.count, ln.s, NoTiming{}, ys, cs);
     if (rc != DDH_OK) return rc;
     DDH_CHECK(hipEventRecord(ln.join, ln.s));
   }
@@ -1057,7 +1166,7 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
   const bool graph = (b->flags & DDH_BATCH_GRAPH) && !b->timing;
   if (b->timing) {
     // per-kernel timing: every lane's launches in sequence on the caller's stream
-    int rc = enqueue_frame(b->dptrs, b->groups, b->total, b->n_k, 1, st, timed, b->yord.data(), b->curord.data());
+    int rc = batch_enqueue(b, b->groups, b->total, st, timed, b->yord.data(), b->curord.data());
     if (rc != DDH_OK) return rc;
   } else if (graph) {
     // the replayed graph reads the frame start from the descriptors
@@ -1389,23 +1498,31 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
   std::vector<const void*> ys(count);
   float2* ybuf = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t ts = nullptr;  // the tuner's own stream: other work on the device is not synchronised with
   std::map<int, TileConfig> start;
   for (int N : sizes) start[N] = tiles_for(N);
-  auto restore = [&](const std::map<int, TileConfig>& m) {
+  auto install = [&](const std::map<int, TileConfig>& m) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto& kv : m) tile_cache()[kv.first] = kv.second;
   };
   auto cleanup = [&]() {
+    if (ts) (void)hipStreamSynchronize(ts);
     for (ddh_stream_t s : ss) ddh_destroy_stream(s);
     if (ybuf) (void)hipFree(ybuf);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    if (ts) (void)hipStreamDestroy(ts);
   };
   size_t px_total = 0;
   for (int i = 0; i < count; ++i) px_total += (size_t)Ns[i] * Ns[i];
-  hipError_t e = hipMalloc(&ybuf, sizeof(float2) * px_total);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(autotune)");
-  e = launch_synth_frames(ybuf, (long long)px_total, 54321u, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "autotune stream");
+  e = hipMalloc(&ybuf, sizeof(float2) * px_total);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipMalloc(autotune)");
+  }
+  e = launch_synth_frames(ybuf, (long long)px_total, 54321u, ts);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) {
@@ -1418,27 +1535,29 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
     ddh_params p;
     ddh_default_params(Ns[i], &p);
     ddh_stream_t s = nullptr;
-    rc = ddh_init_stream(&p, nullptr, nullptr, &s);
+    rc = ddh_init_stream(&p, nullptr, ts, &s);
     if (rc == DDH_OK) ss.push_back(s);
     ys[i] = ybuf + off;
     off += (size_t)Ns[i] * Ns[i];
   }
-  // microseconds per batched step with the installed tilings: best of two
+  // microseconds per batched step with the tilings `tiles` (given to the
+  // timing batch only; the process-wide tilings are not touched): best of two
   // runs of 10 steps after 2 warm-up steps, on a freshly created batch
-  auto time_step = [&](double* out) -> int {
+  auto time_step = [&](const std::map<int, TileConfig>& tiles, double* out) -> int {
     double best = 1e30;
     for (int rep = 0; rep < 2; ++rep) {
       ddh_batch_t b = nullptr;
-      int r = ddh_batch_create(ss.data(), count, 0, &b);
+      int r = batch_create_impl(ss.data(), count, 0, &tiles, &b);
       if (r != DDH_OK) return r;
-      for (int f = 0; f < 2 && r == DDH_OK; ++f) r = ddh_batch_step(b, ys.data(), nullptr);
-      hipError_t he = hipEventRecord(e0, nullptr);
-      for (int f = 0; f < 10 && r == DDH_OK && he == hipSuccess; ++f) r = ddh_batch_step(b, ys.data(), nullptr);
-      if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+      for (int f = 0; f < 2 && r == DDH_OK; ++f) r = ddh_batch_step(b, ys.data(), ts);
+      hipError_t he = hipEventRecord(e0, ts);
+      for (int f = 0; f < 10 && r == DDH_OK && he == hipSuccess; ++f) r = ddh_batch_step(b, ys.data(), ts);
+      if (he == hipSuccess) he = hipEventRecord(e1, ts);
       if (he == hipSuccess) he = hipEventSynchronize(e1);
       float ms = 0.f;
       if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      ddh_batch_destroy(b);
+      (void)hipStreamSynchronize(ts);
+      batch_release(b, false);
       if (r != DDH_OK) return r;
       if (he != hipSuccess) return hip_fail(he, "autotune timing");
       best = std::min(best, 1e3 * (double)ms / 10.0);
@@ -1448,7 +1567,7 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
   };
   std::map<int, TileConfig> cur = start;
   double t_best = 0.0;
-  if (rc == DDH_OK) rc = time_step(&t_best);
+  if (rc == DDH_OK) rc = time_step(cur, &t_best);
   for (int N : sizes) {
     for (int dim = 0; dim < 3 && rc == DDH_OK; ++dim) {
       std::vector<TileConfig> cands;
@@ -1465,24 +1584,19 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
           continue;
         std::map<int, TileConfig> trial = cur;
         trial[N] = c;
-        restore(trial);
         double t = 0.0;
-        rc = time_step(&t);
+        rc = time_step(trial, &t);
         if (rc != DDH_OK) break;
         if (t < 0.99 * t_best) {
           t_best = t;
           cur = trial;
         }
       }
-      restore(cur);
     }
   }
   cleanup();
-  if (rc != DDH_OK) {
-    restore(start);
-    return rc;
-  }
-  restore(cur);
+  if (rc != DDH_OK) return rc;  // nothing was installed
+  install(cur);
   if (cfgs) {
     int k = 0;
     for (int N : sizes) {
@@ -1515,22 +1629,30 @@ int ddh_autotune(int N, int count, int* cfg, double* us) {
   ddh_default_params(N, &p);
   std::vector<ddh_stream_t> ss;
   float2* ybuf = nullptr;
+  hipStream_t ts = nullptr;  // the tuner's own stream (other work is not synchronised with)
   int rc = DDH_OK;
   auto cleanup = [&]() {
+    if (ts) (void)hipStreamSynchronize(ts);
     for (ddh_stream_t s : ss) ddh_destroy_stream(s);
     if (ybuf) (void)hipFree(ybuf);
+    if (ts) (void)hipStreamDestroy(ts);
   };
   const size_t px = (size_t)N * N;
-  hipError_t e = hipMalloc(&ybuf, sizeof(float2) * px * count);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(autotune)");
-  e = launch_synth_frames(ybuf, (long long)(px * count), 12345u, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "autotune stream");
+  e = hipMalloc(&ybuf, sizeof(float2) * px * count);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipMalloc(autotune)");
+  }
+  e = launch_synth_frames(ybuf, (long long)(px * count), 12345u, ts);
   if (e != hipSuccess) {
     cleanup();
     return hip_fail(e, "synth_frames");
   }
   for (int i = 0; i < count && rc == DDH_OK; ++i) {
     ddh_stream_t s = nullptr;
-    rc = ddh_init_stream(&p, nullptr, nullptr, &s);
+    rc = ddh_init_stream(&p, nullptr, ts, &s);
     if (rc == DDH_OK) ss.push_back(s);
   }
   if (rc != DDH_OK) {
@@ -1544,21 +1666,20 @@ int ddh_autotune(int N, int count, int* cfg, double* us) {
   for (int c = 0; c < ncand && rc == DDH_OK; ++c) {
     const int ir = std::min(c, (int)rows.size() - 1), ic = std::min(c, (int)cols.size() - 1),
               im = std::min(c, (int)mss.size() - 1);
-    {
-      std::lock_guard<std::mutex> lk(g_mu);
-      tile_cache()[N] = TileConfig{rows[ir], cols[ic], mss[im].first, mss[im].second};
-    }
+    // the candidate goes to the timing batch only, not to the process-wide tilings
+    const std::map<int, TileConfig> cand{{N, TileConfig{rows[ir], cols[ic], mss[im].first, mss[im].second}}};
     ddh_batch_t b = nullptr;
-    rc = ddh_batch_create(ss.data(), count, 0, &b);
+    rc = batch_create_impl(ss.data(), count, 0, &cand, &b);
     if (rc != DDH_OK) break;
-    for (int f = 0; f < 2 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), nullptr);
+    for (int f = 0; f < 2 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), ts);
     if (rc == DDH_OK) rc = ddh_batch_set_timing(b, 1);
-    for (int f = 0; f < 5 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), nullptr);
+    for (int f = 0; f < 5 && rc == DDH_OK; ++f) rc = ddh_batch_step(b, ys.data(), ts);
     double ms[KK_COUNT];
     long long calls[KK_COUNT];
     int n = KK_COUNT;
     if (rc == DDH_OK) rc = ddh_batch_stage_times(b, ms, calls, nullptr, &n);
-    ddh_batch_destroy(b);
+    (void)hipStreamSynchronize(ts);
+    batch_release(b, false);
     if (rc != DDH_OK) break;
     auto avg = [&](int kk) { return calls[kk] ? 1e3 * ms[kk] / calls[kk] : 1e30; };
     t_rows[ir] = std::min(t_rows[ir], avg(KK_ROW1) + avg(KK_ROW2));
@@ -1569,12 +1690,12 @@ int ddh_autotune(int N, int count, int* cfg, double* us) {
   const int bc = (int)(std::min_element(t_cols.begin(), t_cols.end()) - t_cols.begin());
   const int bm = (int)(std::min_element(t_ms.begin(), t_ms.end()) - t_ms.begin());
   const TileConfig best{rows[br], cols[bc], mss[bm].first, mss[bm].second};
+  cleanup();
+  if (rc != DDH_OK) return rc;  // nothing was installed
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    tile_cache()[N] = rc == DDH_OK ? best : base;
+    tile_cache()[N] = best;
   }
-  cleanup();
-  if (rc != DDH_OK) return rc;
   if (cfg) {
     cfg[0] = best.row_lines;
     cfg[1] = best.col_width;

@@ -212,3 +212,39 @@ def test_workspace_reuse_after_a_larger_call():
     again = D.unrolled_grad(prm, fr, p0, pt, 2)
     assert (first[0], first[2], first[3], first[4]) == (again[0], again[2], again[3], again[4])
     assert torch.equal(first[1], again[1])
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_one_and_two_frames_from_a_loop_state_at_full_size(K):
+    """N = 256 with the paper's q = 1.2, starting from the phase the GPU loop
+    reaches after 20 frames (a realistic state, not a random one): one and two
+    unrolled frames against the FP64 reference to 1e-3.  Here the reference
+    itself moves by about 1e-7 (K = 1) and 2e-6 (K = 2) when phi0 is perturbed
+    by 1e-7, so this bound separates the adjoint's arithmetic from the
+    rounding amplification that longer unrolls show."""
+    torch = _torch()
+    import paper_2305_03284_amd as D
+    N = 256
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=3, stream_id=0))
+    a = O.aperture(N)
+    prm = _params(D, N, st)
+    s = D.Stream(N, prm)
+    for n in range(20):
+        s.step(torch.from_numpy(st.frame(n)).cuda())
+    torch.cuda.synchronize()
+    phi0 = s.phase().cpu().numpy()
+    s.close()
+    frames = [st.frame(20 + k) for k in range(K)]
+    ptrue = st.phase(20 + K - 1).astype(np.float32)
+    L, g, gw, gr, gb = D.unrolled_grad(prm, [torch.from_numpy(f).cuda() for f in frames],
+                                       torch.from_numpy(phi0).cuda(), torch.from_numpy(ptrue).cuda(), 1)
+    Lr, gr_phi, gr_w, gr_r, gr_b = _reference(prm, st, a, frames, phi0, ptrue)
+    g = g.cpu().numpy().astype(np.float64)
+    m = a > 0
+    say(f"N=256 K={K} q=1.2 from a loop state: loss {L:.8f} ref {Lr:.8f}; d_phi0 rel {_rel(g[m], gr_phi[m]):.3e}; "
+        f"d_sigma_w {gw:.6e} vs {gr_w:.6e}; d_sigma_r {gr:.6e} vs {gr_r:.6e}; d_beta {gb:.6e} vs {gr_b:.6e}")
+    assert abs(L - Lr) <= 1e-6 * Lr
+    assert _rel(g[m], gr_phi[m]) < 1e-3
+    assert np.all(g[~m] == 0)
+    for x, y in ((gw, gr_w), (gr, gr_r), (gb, gr_b)):
+        assert abs(x - y) <= 1e-3 * abs(y) + 1e-9

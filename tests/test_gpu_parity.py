@@ -181,6 +181,50 @@ def test_teacher_forced_config1_frames():
     torch.cuda.synchronize()
 
 
+def test_config1_150_frames_teacher_forced_and_free_running():
+    """The streaming workload at full size (N = 256, D/r0 = 15, SNR 5,
+    0.5 px per frame) over 150 frames, the horizon of the paper's Strehl
+    claim.  Teacher-forced: every GPU frame starts from the oracle's previous
+    state and must land within 1e-4 (e_r, e_phi) of the oracle's next state.
+    Free-running: a second GPU stream runs all frames on its own, and its
+    peak Strehl must stay within 0.005 of the free-running oracle's at every
+    frame (the end-to-end pin of the streaming loop)."""
+    D = _ddh()
+    st = synth.config1_stream()
+    N, nf = 256, 150
+    prm, gp = make_pair(N, st.sigma_w2)
+    a = O.aperture(N)
+    tf = D.Stream(N, gp)      # teacher-forced
+    fr = D.Stream(N, gp)      # free-running
+    r_o, p_o = np.zeros((N, N)), np.zeros((N, N))      # oracle, re-rounded to FP32 each frame (teacher)
+    r_f, p_f = np.zeros((N, N)), np.zeros((N, N))      # oracle, free-running in FP64
+    worst_r = worst_p = worst_s = 0.0
+    for n in range(nf):
+        y = st.frame(n)
+        yd = dev(y)
+        yc = y.astype(np.complex128)
+        tf.set_state(dev(r_o, np.float32), dev(p_o, np.float32), n)
+        r_in, p_in = r_o.astype(np.float32).astype(np.float64), p_o.astype(np.float32).astype(np.float64)
+        r_o, p_o = O.ddh_frame(r_in, p_in, yc, a, prm)
+        r_f, p_f = O.ddh_frame(r_f, p_f, yc, a, prm)
+        tf.step(yd)
+        fr.step(yd)
+        r_g, p_g = state(tf)
+        er, ep = M.rel_l2(r_g, r_o), M.phase_rms_diff(p_g, p_o, a)
+        truth = st.phase(n)
+        s_gpu = fr.strehl(dev(truth, np.float32))
+        s_orc = M.strehl(p_f, truth, a)
+        worst_r, worst_p, worst_s = max(worst_r, er), max(worst_p, ep), max(worst_s, abs(s_gpu - s_orc))
+        if n % 25 == 0 or n == nf - 1:
+            say(f"config-1 frame {n}: e_r={er:.2e} e_phi={ep:.2e} S gpu {s_gpu:.4f} oracle {s_orc:.4f}")
+        assert er < TOL_R and ep < TOL_PHI, (n, er, ep)
+        assert np.all(p_g[a == 0] == 0.0)
+        assert abs(s_gpu - s_orc) <= TOL_S, (n, s_gpu, s_orc)
+    say(f"config-1 over {nf} frames: worst e_r {worst_r:.2e}, e_phi {worst_p:.2e}, |dS| {worst_s:.2e}")
+    tf.close()
+    fr.close()
+
+
 def test_config0_em_iterations_and_cost():
     """Plain loop on one frame: DDH prologue then EM iterations; GPU FP64 cost
     is non-increasing (up to FP32 rounding of the state) and equals the
