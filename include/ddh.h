@@ -207,7 +207,9 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
  * words; its state is then unspecified: restore it with ddh_set_state (which
  * also clears those words) before its next frame.  DDH_BATCH_TEST_GIVEUP (with
  * DDH_BATCH_WORKLIST; for tests of that failure path only) makes every such
- * wait give up at once. */
+ * wait give up at once.  Within a queue the stages of one stream are spread
+ * by `lag` streams' worth of items (environment variable DDH_WORKLIST_LAG at
+ * batch creation, 1..64, default 2), so that an item rarely waits. */
 #define DDH_BATCH_WORKLIST 2
 #define DDH_BATCH_TEST_GIVEUP 4
 int ddh_batch_create(const ddh_stream_t* streams, int count, int flags, ddh_batch_t* out);

@@ -812,26 +812,32 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
 // the eager kernel of its stage, so every result is bit for bit the eager
 // path's.
 //
-// Work list.  Stream s is dealt to queue s % nq.  A queue's tickets form
-// slots of SLOT = nA + nB + nC + nD items: at slot j the stats items of the
-// queue's stream j, the row1 items of its stream j - lag, the column items of
-// j - 2 lag and the row2 items of j - 3 lag (items of streams out of range
-// are empty; without a stats stage, k > 0, the other stages move up one
-// place).  An item waits until every item of the previous stage of its stream
-// has completed; those carry smaller tickets of the same queue and have been
-// claimed before it, so each wait is on work that is already running or
-// done: the list cannot deadlock.  Waits are bounded by spin_limit polls; a
-// wait that gives up sets the stream's give-up word and the item runs anyway,
-// so every workgroup ends (giveup != 0 forces this, for tests).
+// Work list.  Stream s is dealt to queue s % nq.  A queue's items are
+// numbered slot by slot: at slot j the stats items of the queue's stream j,
+// the row1 items of its stream j - lag, the column items of j - 2 lag and
+// the row2 items of j - 3 lag, those streams that exist (without a stats
+// stage, k > 0, the other stages move up one place).  An item waits until
+// every item of the previous stage of its stream has completed; those carry
+// smaller numbers of the same queue.  A workgroup claims its next number
+// while it runs its current item; the smallest unfinished item is then always
+// some workgroup's current item (a workgroup's claimed-ahead item is larger
+// than its current one), and every item it waits on is smaller, hence
+// finished: the list cannot deadlock.  Waits are bounded by spin_limit polls;
+// a wait that gives up sets the stream's give-up word and the item runs
+// anyway, so every workgroup ends (giveup != 0 forces this, for tests).
 //
 // Coherence.  A workgroup claims from the queue of the XCD it runs on (the
-// hardware XCC_ID register), so every item of a stream runs on one XCD,
-// whose L2 all its CUs share.  A producer's stores have completed (vmcnt(0))
-// before its completion counter is incremented at L2, and a consumer first
-// touches the produced data (through L1 and L2) after it has read the counter
-// there; within a launch each produced array is read only after it is
-// written.  Frame arguments reach every stage from the kernel arguments, so
-// no stage reads a descriptor field that this launch writes.
+// hardware XCC_ID register), so every item of a stream runs on one XCD, whose
+// L2 all its CUs share: synchronisation is at XCD scope, as for a workgroup
+// split over CUs.  Release: each wave's stores have completed at the L2
+// (vmcnt(0)) before the barrier after which the completion count is
+// incremented there.  Acquire: the waiting wave reads the count at the L2
+// and then invalidates its CU's L1 before the barrier that lets the item's
+// waves read, so no line cached on this CU before the producers wrote it is
+// read.  (Agent-scope fences, which write back and invalidate the L2 at every
+// item, are not needed for this and cost about twice the step time.)  Frame
+// arguments reach every stage from the kernel arguments, so no stage reads a
+// descriptor field that this launch writes.
 //
 // The last workgroup to finish resets the queue tickets, and the last row2
 // item of a stream its stage counters, so the next launch starts from zero.
@@ -850,6 +856,14 @@ __device__ __forceinline__ unsigned xcc_id() {
   // hwreg(HW_REG_XCC_ID, 0, 4): the XCD the wave runs on
   return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
 }
+// Invalidate this CU's vector L1 (lines another CU of the XCD may have
+// rewritten since they were cached here); the L2 is the XCD's coherence point.
+__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
+// lgkmcnt(0): this wave's LDS stores have completed.  Issued after the store
+// of the next ticket, which the loop-top barrier publishes: on that loop's
+// back edge the compiler has been seen to place no LDS wait before the
+// barrier, and another wave could then read the previous ticket.
+__device__ __forceinline__ void lds_stores_done() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 __device__ __forceinline__ unsigned ctl_load(unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -867,42 +881,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   __shared__ int s_ticket;
   const int fin = k == 0, first = (mode && k == 0) ? 1 : 0;
   const int nA = fin ? (N * N) / STATS_PIX_PER_BLOCK : 0, nB = N / LPW, nC = N / W, nD = N / LPW;
-  const int SLOT = nA + nB + nC + nD;
   const int s0 = fin ? 0 : 1;  // first stage present
   const int q = (int)(xcc_id() % (unsigned)nq);
   const int Sq = q < count ? (count - q + nq - 1) / nq : 0;
-  const int tickets = Sq > 0 ? (Sq + (3 - s0) * lag) * SLOT : 0;
   const int need[4] = {nA, nB, nC, nD};
+  const int tickets = Sq * (nA + nB + nC + nD);  // only real items are numbered
   for (int i = threadIdx.x; i < N; i += 256) s_tw[i] = tw[i];
+  if (threadIdx.x == 0) {
+    s_ticket = (int)atomicAdd(ctl0 + CTL_TICKETS + q, 1u);
+    lds_stores_done();
+  }
+  int next = 0;  // thread 0: the ticket claimed ahead for the next item
   for (;;) {
-    __syncthreads();  // the previous item is done with the LDS (and s_ticket)
-    if (threadIdx.x == 0) s_ticket = (int)atomicAdd(ctl0 + CTL_TICKETS + q, 1u);
-    __syncthreads();
+    __syncthreads();  // s_ticket is written, and the previous item is done with the LDS
     const int t = s_ticket;
     if (t >= tickets) break;
-    const int slot = t / SLOT, pos = t - slot * SLOT;
-    int stage, item;
-    if (pos < nA) {
-      stage = 0;
-      item = pos;
-    } else if (pos < nA + nB) {
-      stage = 1;
-      item = pos - nA;
-    } else if (pos < nA + nB + nC) {
-      stage = 2;
-      item = pos - nA - nB;
-    } else {
-      stage = 3;
-      item = pos - nA - nB - nC;
+    // claim the next item now: the atomic's round trip overlaps this item
+    if (threadIdx.x == 0) next = (int)atomicAdd(ctl0 + CTL_TICKETS + q, 1u);
+    // ticket -> (stage, queue position of the stream, item): walk the slots;
+    // at slot j the queue's streams j, j - lag, j - 2 lag, j - 3 lag (those
+    // in range) contribute the items of stages s0, s0 + 1, ... in that order
+    int stage = s0, jq = 0, item = 0;
+    {
+      int rem = t;
+      for (int j = 0;; ++j) {
+        bool found = false;
+        for (int st = s0; st < 4; ++st) {
+          const int i = j - (st - s0) * lag;
+          if (i < 0 || i >= Sq) continue;
+          if (rem < need[st]) {
+            stage = st;
+            jq = i;
+            item = rem;
+            found = true;
+            break;
+          }
+          rem -= need[st];
+        }
+        if (found) break;
+      }
     }
-    const int j = slot - (stage - s0) * lag;
-    if (j < 0 || j >= Sq) continue;  // empty item
+    const int strm = jq * nq + q;
     // the thread index, opaque to the compiler in each item: otherwise every
     // stage's per-thread index arithmetic is hoisted out of the loop and all
     // of it stays live at once
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int strm = j * nq + q;
     StreamDesc* const dp = use_args == 2 ? a.d[strm] : dptrs[strm];
     const auto& D = desc_ref(dp);
     const float2* y = use_args ? a.y[strm] : D.y;
@@ -919,6 +943,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
           }
           __builtin_amdgcn_s_sleep(2);
         }
+        // acquire within the XCD: this CU's L1 is invalidated, so the loads
+        // below miss to the L2 that the producers' stores have reached
+        l1_invalidate();
       }
       __syncthreads();
     }
@@ -939,7 +966,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     } else {
       row2_body<N, LPW, false>(D, y, cur, item, tw, k, first, mat, lds, s_tw, tid);
     }
-    // ---- completion: every store of the item has reached L2 first
+    // ---- completion (release within the XCD): every wave's stores have
+    // reached the L2 (vmcnt(0)) before the barrier, and the count follows it
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -947,6 +975,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       if (stage == 3 && done + 1 == (unsigned)nD) {
         for (int g = 0; g < 4; ++g) __hip_atomic_store(ctl + CTL_STAGE + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      s_ticket = next;
+      lds_stores_done();
     }
   }
   if (threadIdx.x == 0 && atomicAdd(ctl0 + CTL_FINISHED, 1u) + 1 == gridDim.x) {

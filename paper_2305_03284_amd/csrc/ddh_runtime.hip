@@ -1011,6 +1011,7 @@ static int batch_create_impl(const ddh_stream_t* streams, int count, int flags,
   b->worklist = (flags & DDH_BATCH_WORKLIST) != 0;
   b->wl.nq = xcd_count(dev);
   b->wl.giveup = (flags & DDH_BATCH_TEST_GIVEUP) ? 1 : 0;
+  if (const char* lag = getenv("DDH_WORKLIST_LAG")) b->wl.lag = std::max(1, std::min(64, atoi(lag)));
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
   if (e != hipSuccess) {
     delete b;
