@@ -1018,14 +1018,16 @@ __device__ __forceinline__ float cubic_f(float A, float B, float s, float x) {
   DDH_EXACT_FP
   return __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A, x, -B), x, 1.0f), x, -s);
 }
+// Guarded Newton steps on the cubic; A3 = 3A and B2 = 2B are the derivative's
+// coefficients, formed once per pixel by the caller.
 template <int IT>
-__device__ __forceinline__ float polish(float A, float B, float s, float x) {
+__device__ __forceinline__ float polish(float A, float B, float A3, float B2, float s, float x) {
   DDH_EXACT_FP
   float f = cubic_f(A, B, s, x);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const float fp = __builtin_fmaf(__builtin_fmaf(3.0f * A, x, -2.0f * B), x, 1.0f);
-    const float xn = x - f * frcp(fp);
+    const float fp = __builtin_fmaf(__builtin_fmaf(A3, x, -B2), x, 1.0f);
+    const float xn = __builtin_fmaf(-f, frcp(fp), x);
     const float fn = cubic_f(A, B, s, xn);
     const bool take = (xn > 0.0f) && (fabsf(fn) < fabsf(f));
     x = take ? xn : x;
@@ -1033,35 +1035,39 @@ __device__ __forceinline__ float polish(float A, float B, float s, float x) {
   }
   return x;
 }
+// Depressed form: rho = t + b3 with b3 = B/(3A), c = 1/A, gives
+// t^3 + p t + q = 0, p = c - 3 b3^2, q = c (b3 - s) - 2 b3^3, and the
+// discriminant q^2/4 + p^3/27 (>= 0: one real root).
 __device__ __forceinline__ float solve_r(float s, float A, float B) {
   DDH_EXACT_FP
   if (!(A > 0.0f)) return s;
-  const float iA = frcp(A);
-  const float a2 = -B * iA, a1 = iA, a0 = -s * iA;
-  const float sh = -a2 * (1.0f / 3.0f);
-  const float p = a1 - a2 * a2 * (1.0f / 3.0f);
-  const float q = (2.0f / 27.0f) * a2 * a2 * a2 - a2 * a1 * (1.0f / 3.0f) + a0;
-  const float disc = 0.25f * q * q + (1.0f / 27.0f) * p * p * p;
+  const float c = frcp(A);
+  const float b3 = (B * c) * (1.0f / 3.0f);
+  const float p = __builtin_fmaf(-3.0f * b3, b3, c);
+  const float b3sq = b3 * b3;
+  const float q = __builtin_fmaf(c, b3 - s, (-2.0f * b3sq) * b3);
+  const float disc = __builtin_fmaf(0.25f * q, q, (p * (1.0f / 27.0f)) * (p * p));
+  const float A3 = 3.0f * A, B2 = 2.0f * B;
   if (disc >= 0.0f || p >= 0.0f) {
     const float sq = fsqrt(fmaxf(disc, 0.0f));
-    const float u = fcbrt(-0.5f * q - copysignf(sq, q));
-    const float t = (u != 0.0f) ? u - p * frcp(3.0f * u) : 0.0f;
-    float x = t + sh;
+    const float u = fcbrt(__builtin_fmaf(-0.5f, q, -copysignf(sq, q)));
+    const float t = (u != 0.0f) ? __builtin_fmaf(-p, frcp(3.0f * u), u) : 0.0f;
+    float x = t + b3;
     if (!(x > 0.0f) || !isfinite(x)) x = s;
-    return polish<1>(A, B, s, x);
+    return polish<1>(A, B, A3, B2, s, x);
   }
+  // three real roots: t_k = 2 m cos(th - k/3 rev), m = sqrt(-p/3),
+  // th = acos(arg)/3 in [0, 1/6] rev; k = 0 gives the largest root and
+  // k = 2 the smallest (the middle one is a local maximum of h)
   const float m = fsqrt(-p * (1.0f / 3.0f));
   float arg = (1.5f * q * frcp(p)) * fsqrt(-3.0f * frcp(p));
   arg = fminf(1.0f, fmaxf(-1.0f, arg));
-  // th = acos(arg)/3 in revolutions
   const float th = acosf(arg) * (1.0f / (6.0f * 3.14159265358979323846f));
-  const float x1 = 2.0f * m * fcos_rev(th) + sh;
-  const float x2 = 2.0f * m * fcos_rev(th - (1.0f / 3.0f)) + sh;
-  const float x3 = 2.0f * m * fcos_rev(th - (2.0f / 3.0f)) + sh;
-  float lo = fminf(fminf(x1, x2), x3), hi = fmaxf(fmaxf(x1, x2), x3);
+  float hi = __builtin_fmaf(2.0f * m, fcos_rev(th), b3);
+  float lo = __builtin_fmaf(2.0f * m, fcos_rev(th - (2.0f / 3.0f)), b3);
   if (!(lo > 0.0f)) lo = fminf(s, hi);
-  lo = polish<2>(A, B, s, lo);
-  hi = polish<2>(A, B, s, hi);
+  lo = polish<2>(A, B, A3, B2, s, lo);
+  hi = polish<2>(A, B, A3, B2, s, hi);
   // h(lo) - h(hi) as one difference
   const float dh = 0.69314718055994531f * flog2(lo * frcp(hi)) + s * (hi - lo) * frcp(lo * hi) +
                    (lo - hi) * (0.5f * A * (lo + hi) - B);
@@ -1093,12 +1099,13 @@ enum : int { NB_UP = 1, NB_DN = 2, NB_LF = 4, NB_RT = 8, NB_ALL = 15 };
 __device__ __forceinline__ int nb_mask(int gi, int gj, int N) {
   return (gi > 0 ? NB_UP : 0) | (gi < N - 1 ? NB_DN : 0) | (gj > 0 ? NB_LF : 0) | (gj < N - 1 ? NB_RT : 0);
 }
-// r update of one pixel from its 8 neighbours.  CHECK: some neighbours may be
-// off the grid (mask bits clear); their weight is zero and their staged value
-// is finite.
+// r update of one pixel from its 8 neighbours, with the edge and diagonal
+// prior weights wE = inv_sp/6 and wD = inv_sp/12.  CHECK: some neighbours may
+// be off the grid (mask bits clear); their weight is zero and their staged
+// value is finite.
 template <bool CHECK>
-__device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], int mask, float inv_sp,
-                                         float lc, float pmq, float qop, float fl) {
+__device__ __forceinline__ float r_pixel_w(float rp, float s, const float (&rq)[8], int mask, float wE, float wD,
+                                           float lc, float pmq, float qop, float fl) {
   DDH_EXACT_FP
   float Ae = 0.f, Be = 0.f, Ad = 0.f, Bd = 0.f;
 #pragma unroll
@@ -1119,9 +1126,15 @@ __device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8]
       Bd = __builtin_fmaf(sh, rq[e], Bd);
     }
   }
-  const float wE = inv_sp * (1.0f / 6.0f), wD = inv_sp * (1.0f / 12.0f);
   const float A = __builtin_fmaf(wE, Ae, wD * Ad), B = __builtin_fmaf(wE, Be, wD * Bd);
   return fmaxf(solve_r(s, A, B), fl);
+}
+
+// the same with the weights formed from inv_sp = 1/sigma^p
+template <bool CHECK>
+__device__ __forceinline__ float r_pixel(float rp, float s, const float (&rq)[8], int mask, float inv_sp,
+                                         float lc, float pmq, float qop, float fl) {
+  return r_pixel_w<CHECK>(rp, s, rq, mask, inv_sp * (1.0f / 6.0f), inv_sp * (1.0f / 12.0f), lc, pmq, qop, fl);
 }
 // phi update of one pupil pixel; pq holds the neighbours' phases (zero off
 // the pupil and off the grid), P the prior weight of the pupil neighbours
@@ -1329,6 +1342,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
     os[slot] = opk[slot] >= 0 ? second_moment(wiener_of(sR[opk[slot] & 0xffff], s2), os[slot], s2) : 0.f;
   }
   const float inv_sp = D.qg_inv_sp, lc = D.qg_lc, pmq = D.qg_pmq, qop = D.qg_qop;
+  const float wE = inv_sp * (1.0f / 6.0f), wD = inv_sp * (1.0f / 12.0f);
   // ---- the four colour passes (same-colour pixels are never neighbours, so
   // each pass updates its pixels in place).  The neighbour-mask test is
   // compiled only into the path of the tiles at the grid border, a
@@ -1346,7 +1360,7 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
           float rq[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) rq[e] = sR[o + offs[e]];
-          const float rn = r_pixel<CHECK>(sR[o], os[slot], rq, (pk >> 16) & NB_ALL, inv_sp, lc, pmq, qop, fl);
+          const float rn = r_pixel_w<CHECK>(sR[o], os[slot], rq, (pk >> 16) & NB_ALL, wE, wD, lc, pmq, qop, fl);
           if (pk & (1 << 24)) {
             float pq[8];
 #pragma unroll
