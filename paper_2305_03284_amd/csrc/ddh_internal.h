@@ -118,10 +118,12 @@ hipError_t launch_mstep(StreamDesc* const* dptrs, int count, int N, int k, int u
 // spin_limit: polls before a wait gives up; giveup != 0 makes every wait
 // give up at once (failure-path tests).  whole_image: the M-step runs as
 // whole-image colour passes (the column and row2 stages then also write the
-// passes' working copies of r and phi).
+// passes' working copies of r and phi).  share in (0, 1]: the part of the
+// device this launch may fill (its persistent grid is that fraction of three
+// workgroups per CU), for launches of several groups that run at once.
 hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int mode,
                         const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned* ctl0, int nq,
-                        int lag, unsigned spin_limit, int giveup, int whole_image, hipStream_t st);
+                        int lag, unsigned spin_limit, int giveup, int whole_image, float share, hipStream_t st);
 
 // Plain batched unitary 2D DFT (no fusion): rows into work, columns into out.
 hipError_t launch_fft2(int N, int count, const float2* in, float2* out, float2* work,

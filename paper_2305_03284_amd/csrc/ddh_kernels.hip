@@ -839,6 +839,11 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row2(StreamDesc* const
 // arguments reach every stage from the kernel arguments, so no stage reads a
 // descriptor field that this launch writes.
 //
+// Every queue is served only if the dispatcher places workgroups on every
+// XCD (it deals them out round-robin; the grid is a multiple of nq).  The
+// last workgroup to finish checks that every queue's tickets were all
+// claimed and otherwise sets the give-up word of that queue's streams, so
+// such a frame is reported, not silently left undone.
 // The last workgroup to finish resets the queue tickets, and the last row2
 // item of a stream its stage counters, so the next launch starts from zero.
 // grid: persistent, a multiple of nq; block 256 (LPW, W chosen so that each
@@ -980,6 +985,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
   }
   if (threadIdx.x == 0 && atomicAdd(ctl0 + CTL_FINISHED, 1u) + 1 == gridDim.x) {
+    // a queue that no workgroup served (the dispatcher put none on its XCD)
+    // left its streams' items undone: their give-up words say so
+    for (int g = 0; g < nq && g < count; ++g) {
+      const int sq = (count - g + nq - 1) / nq;
+      // read with an atomic: the counter was updated on another XCD
+      if (atomicAdd(ctl0 + CTL_TICKETS + g, 0u) < (unsigned)(sq * (nA + nB + nC + nD)))
+        for (int j = 0; j < sq; ++j) {
+          const int strm = j * nq + g;
+          StreamDesc* const dp = use_args == 2 ? a.d[strm] : dptrs[strm];
+          __hip_atomic_store(desc_ref(dp).ctl + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     for (int g = 0; g < CTL_MAX_QUEUES; ++g)
       __hip_atomic_store(ctl0 + CTL_TICKETS + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(ctl0 + CTL_FINISHED, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1868,11 +1885,12 @@ hipError_t launch_mstep(StreamDesc* const* d, int count, int N, int k, int use_p
 
 hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int mode,
                         const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned* ctl0, int nq,
-                        int lag, unsigned spin_limit, int giveup, int whole_image, hipStream_t st) {
-  if (nq < 1 || nq > CTL_MAX_QUEUES || lag < 1) return hipErrorInvalidValue;
+                        int lag, unsigned spin_limit, int giveup, int whole_image, float share, hipStream_t st) {
+  if (nq < 1 || nq > CTL_MAX_QUEUES || lag < 1 || !(share > 0.0f) || share > 1.0f) return hipErrorInvalidValue;
   StreamDesc** list = const_cast<StreamDesc**>(dptrs);
   // persistent grid: 3 workgroups of 256 threads per CU (the column stage's
-  // registers allow 3 waves per SIMD), a multiple of nq, no more than items
+  // registers allow 3 waves per SIMD) times the launch's share of the device,
+  // a multiple of nq, no more than items
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
@@ -1886,7 +1904,8 @@ hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2
       }
     const int use_args = ys ? (ds ? 2 : 1) : 0;
     const int per_stream = 4 * N;  // upper bound of the items of one stream
-    int grid = 3 * cus;
+    int grid = (int)(3.0f * (float)cus * share + 0.5f);
+    if (grid < nq) grid = nq;
     if (grid > n * per_stream) grid = n * per_stream;
     grid = ((grid + nq - 1) / nq) * nq;
     unsigned* c0 = ctl0;

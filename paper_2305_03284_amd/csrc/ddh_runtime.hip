@@ -288,6 +288,7 @@ struct Group {
   TileConfig tc;
   const float2* tw;
   unsigned* ctl0 = nullptr;  // work-list control words of the group's launch (its first stream's)
+  float share = 1.0f;        // part of the device its work-list launch fills (lanes running at once)
 };
 
 // Work-list (persistent frame kernel) settings of a batch.
@@ -430,7 +431,7 @@ int enqueue_frame_worklist(StreamDesc** dptrs, const Group* groups, int ngroups,
       e = around(KK_FRAME, [&] {
         return launch_frame(dptrs + g.off, g.count, g.N, g.tw, k, mode, args ? ys + g.off : nullptr,
                             args ? curs + g.off : nullptr, args && ds ? ds + g.off : nullptr, g.ctl0, wl.nq, wl.lag,
-                            wl.spin, wl.giveup, g.tc.m_tile_h == 0, st);
+                            wl.spin, wl.giveup, g.tc.m_tile_h == 0, g.share, st);
       });
       if (e != hipSuccess) return hip_fail(e, "launch_frame");
     }
@@ -1000,8 +1001,12 @@ static int batch_create_impl(const ddh_stream_t* streams, int count, int flags,
         g.tw = streams[i]->tw;
       }
       if (g.count) {
+        b->groups.push_back(g);  // the timed path runs every group alone
+        // lanes run at once: each work-list launch fills its lane's part of the device
+        long long all = 0;
+        for (long long v : load) all += v;
+        if (nlanes > 1 && all > 0) g.share = std::max(0.05f, (float)((double)load[l] / (double)all));
         ln.groups.push_back(g);
-        b->groups.push_back(g);
       }
     }
     ln.count = (int)order.size() - ln.off;

@@ -122,3 +122,40 @@ def test_worklist_gives_up_and_every_launch_ends():
     for (r0, p0), (r1, p1) in zip(ref, got):
         np.testing.assert_array_equal(r1, r0)
         np.testing.assert_array_equal(p1, p0)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_worklist_stays_identical_over_repeated_concurrent_groups(graph):
+    """Four N groups whose work-list launches run at once (one lane each),
+    repeated: every repetition must give the default launches' result bit for
+    bit and no wait may give up.  (Waves of one workgroup once read different
+    tickets when the loop-top barrier was not preceded by a wait for the
+    ticket's LDS store; under this load that showed in about a fifth of the
+    runs.)"""
+    D = _ddh()
+    torch = _torch()
+    Ns = [128, 256, 64, 256, 512, 128, 64, 256]
+    sims, cases = _cases(Ns, 33)
+    nfr, reps = 3, 40
+    frames = [[dev(sm.frame(n)) for n in range(nfr)] for sm in sims]
+    ref = _run(D, cases, frames, nfr, graph=False)
+    streams = [D.Stream(N, gp) for (N, gp) in cases]
+    b = D.Batch(streams, graph=graph, worklist=True)
+    zs = {N: torch.zeros((N, N), dtype=torch.float32, device="cuda") for N in set(Ns)}
+    say(f"work list, four concurrent groups, graph={graph}: {reps} repetitions of {nfr} frames")
+    bad = []
+    try:
+        for rep in range(reps):
+            for s, N in zip(streams, Ns):
+                s.set_state(zs[N], zs[N], 0)
+            for n in range(nfr):
+                b.step([frames[i][n] for i in range(len(Ns))])
+            got = [state(s) for s in streams]
+            assert [s.status() for s in streams] == [D.DDH_OK] * len(Ns)
+            bad += [(rep, i) for i, ((r0, p0), (r1, p1)) in enumerate(zip(ref, got))
+                    if not (np.array_equal(r0, r1) and np.array_equal(p0, p1))]
+    finally:
+        b.close()
+        for s in streams:
+            s.close()
+    assert not bad, bad[:10]
