@@ -869,8 +869,11 @@ __device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" 
 // back edge the compiler has been seen to place no LDS wait before the
 // barrier, and another wave could then read the previous ticket.
 __device__ __forceinline__ void lds_stores_done() { __builtin_amdgcn_s_waitcnt(0xC07F); }
-__device__ __forceinline__ unsigned ctl_load(unsigned* p) {
+__device__ __forceinline__ unsigned ctl_load(gptr<unsigned> p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ctl_add(gptr<unsigned> p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int N>
@@ -936,7 +939,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const auto& D = desc_ref(dp);
     const float2* y = use_args ? a.y[strm] : D.y;
     const int cur = use_args ? a.cur[strm] : D.cur;
-    unsigned* ctl = D.ctl;
+    const auto ctl = glb(D.ctl);  // global, not flat, atomics
     // ---- wait for the previous stage of this stream
     if (stage > s0) {
       if (threadIdx.x == 0) {
@@ -976,7 +979,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
-      const unsigned done = atomicAdd(ctl + CTL_STAGE + stage, 1u);
+      const unsigned done = ctl_add(ctl + CTL_STAGE + stage, 1u);
       if (stage == 3 && done + 1 == (unsigned)nD) {
         for (int g = 0; g < 4; ++g) __hip_atomic_store(ctl + CTL_STAGE + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -994,7 +997,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         for (int j = 0; j < sq; ++j) {
           const int strm = j * nq + g;
           StreamDesc* const dp = use_args == 2 ? a.d[strm] : dptrs[strm];
-          __hip_atomic_store(desc_ref(dp).ctl + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(glb(desc_ref(dp).ctl) + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     for (int g = 0; g < CTL_MAX_QUEUES; ++g)
@@ -1240,11 +1243,14 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   const int ti = tile / TPC, tj = tile - ti * TPC;
   const int gi0 = ti * TH - 4, gj0 = tj * TW - 4;
   const int in = (D.cur + k) & 1;
-  const float* rin = glb(D.r[in]);
-  const float* pin = glb(D.phi[in]);
-  float* rout = glb(D.r[in ^ 1]);
-  float* pout = glb(D.phi[in ^ 1]);
-  const float* sc = glb(D.scal);
+  // global (address space 1) pointers throughout: through generic pointers
+  // the compiler emits flat loads, which also count against the LDS wait
+  // counter
+  const auto rin = glb(D.r[in]);
+  const auto pin = glb(D.phi[in]);
+  const auto rout = glb(D.r[in ^ 1]);
+  const auto pout = glb(D.phi[in ^ 1]);
+  const auto sc = glb(D.scal);
   const float s2 = D.sigma2, lam = D.lam, alpha = D.alpha, fl = D.r_floor, beta2 = 2.0f * D.beta;
   // ---- every global read is issued up front: r, |b|^2 and phi of the
   // region in 4-pixel vectors with their aperture bytes (the halo is 4 wide
@@ -1255,9 +1261,11 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   // and read their whole region without bounds tests.
   constexpr int RW4 = RW / 4, RP4 = G::RH * RW4;
   constexpr int SR = (RP4 + BT - 1) / BT;
-  const float4* rin4 = reinterpret_cast<const float4*>(rin);
-  const float4* pin4 = reinterpret_cast<const float4*>(pin);
-  const float4* bb4 = reinterpret_cast<const float4*>(glb(D.bb));
+  const auto rin4 = reinterpret_cast<gptr<const float4>>(rin);
+  const auto pin4 = reinterpret_cast<gptr<const float4>>(pin);
+  const auto bb4 = reinterpret_cast<gptr<const float4>>(glb(D.bb));
+  const auto rout4 = reinterpret_cast<gptr<float4>>(rout);
+  const auto pout4 = reinterpret_cast<gptr<float4>>(pout);
   const auto ktp = glb(D.T);
   const auto bbp = glb(D.bb);
   const auto geop = glb(D.geo);
@@ -1321,8 +1329,8 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
     for (int idx = threadIdx.x; idx < TH * (TW / 4); idx += BT) {
       const int li = idx / (TW / 4);
       const int v = ((ti * TH + li) * N + tj * TW) / 4 + (idx - li * (TW / 4));
-      reinterpret_cast<float4*>(rout)[v] = rin4[v];
-      reinterpret_cast<float4*>(pout)[v] = pin4[v];
+      rout4[v] = rin4[v];
+      pout4[v] = pin4[v];
     }
     return;
   }
@@ -1399,8 +1407,8 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
     const int li = idx / (TW / 4), c4 = idx - li * (TW / 4);
     const int o4 = (4 + li) * RW4 + 1 + c4;
     const int v = ((ti * TH + li) * N + tj * TW) / 4 + c4;
-    reinterpret_cast<float4*>(rout)[v] = reinterpret_cast<const float4*>(sR)[o4];
-    reinterpret_cast<float4*>(pout)[v] = reinterpret_cast<const float4*>(sP)[o4];
+    rout4[v] = reinterpret_cast<const float4*>(sR)[o4];
+    pout4[v] = reinterpret_cast<const float4*>(sP)[o4];
   }
 }
 
@@ -2061,8 +2069,8 @@ __global__ __launch_bounds__(256) void k_g_stats(const float2* const* ys, const 
                                                  double* part) {
   const int N = Pd[blockIdx.y].N;
   const float d2 = Pd[blockIdx.y].d2;
-  const float2* y = ys[blockIdx.y];
-  const float* ph = phi + (size_t)blockIdx.y * N * N;
+  const auto y = glb(ys[blockIdx.y]);  // global, not flat, loads
+  const auto ph = glb(phi) + (size_t)blockIdx.y * N * N;
   float2 v[16];
   float f[16];
 #pragma unroll
