@@ -1092,10 +1092,16 @@ int ddh_batch_set_timing(ddh_batch_t b, int enable) {
   return DDH_OK;
 }
 
+// Timing-only events: without the system-scope fence at each record, which
+// would write back and invalidate the L2 between the timed kernels and make
+// each kernel start with cold caches (its inputs were just written by the
+// previous kernel).
+static hipError_t timing_event(hipEvent_t* ev) { return hipEventCreateWithFlags(ev, hipEventDisableSystemFence); }
+
 static hipEvent_t pool_event(ddh_batch_t b) {
   if (b->pool_used == b->pool.size()) {
     hipEvent_t ev;
-    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    if (timing_event(&ev) != hipSuccess) return nullptr;
     b->pool.push_back(ev);
   }
   return b->pool[b->pool_used++];
@@ -1529,8 +1535,8 @@ int ddh_autotune_mix(const int* Ns, int count, int* cfgs, double* step_us) {
     return hip_fail(e, "hipMalloc(autotune)");
   }
   e = launch_synth_frames(ybuf, (long long)px_total, 54321u, ts);
-  if (e == hipSuccess) e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = timing_event(&e0);
+  if (e == hipSuccess) e = timing_event(&e1);
   if (e != hipSuccess) {
     cleanup();
     return hip_fail(e, "autotune setup");
