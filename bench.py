@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--cpu-frames-per-core", type=int, default=30)
     p.add_argument("--mixed-steps", type=int, default=100)
     p.add_argument("--no-extras", action="store_true", help="only the timed batched step (for profiling)")
+    p.add_argument("--no-serve-grad", action="store_true", help="leave out the serving and gradient summaries")
     p.add_argument("--autotune", action="store_true", help="time every tiling first and keep the fastest")
     p.add_argument("--autotune-mix", action="store_true",
                    help="tune the tilings of all sizes together on the whole batched step")
@@ -214,7 +215,7 @@ def oracle_all_cores(specs, n_frames):
                       f"workload, FP64 NumPy, 1 thread per process, {span:.1f} s span"}
 
 
-def serve_main(args):
+def serve_main(args, only=None, emit=True):
     """Serving workload: 32 streams, N in {128, 256} (1:1, seeded), frames
     arriving by a Poisson process at --serve-rate aggregate, streams starting
     within the first 50 ms, --serve-frames frames each (8 distinct frames per
@@ -243,6 +244,8 @@ def serve_main(args):
     total_bytes = sum(nbytes.values())
     runs = [("trace", args.serve_rate, total_bytes), ("trace_budget", args.serve_rate, budget),
             ("trace_10x", 10 * args.serve_rate, total_bytes), ("saturation", None, total_bytes)]
+    if only is not None:
+        runs = [r for r in runs if r[0] in only]
     for label, rate, bud in runs:
         rate_reqs = poisson_requests(keys, rate or args.serve_rate, args.serve_frames, seed=4,
                                      start_spread_s=0.0 if rate is None else 0.05)
@@ -275,7 +278,9 @@ def serve_main(args):
     tr = out["trace"]["continuous_batching"]
     out.update({"p50_ms": tr["p50_ms"], "p99_ms": tr["p99_ms"], "frames_per_s": tr["frames_per_s"],
                 "mean_strehl": tr["mean_strehl"]})
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def _quality_stream_frames(args):
@@ -360,7 +365,7 @@ def quality_main(args, pre):
     print(json.dumps(out), flush=True)
 
 
-def grad_main(args):
+def grad_main(args, emit=True):
     """Differentiation workload: 16 streams at N=256, each with the gradient
     of K=8 unrolled DDH frames (from r = 0 and a perturbed phase) with respect
     to phi0, sigma_w, sigma_r and beta_phi, checkpoints every 2 frames.  The
@@ -414,7 +419,7 @@ def grad_main(args):
                       "streams": S, "N": N, "K": K, "ckpt": ckpt},
            "one_stream_at_a_time": {"frames_per_s": S * K / dt1, "ms_per_step": dt1 * 1e3},
            "mean_loss": float(np.mean([r[0] for r in res]))}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and emit:
         from oracle import grad as G
         from oracle import ddh as O
         st, frames, phi0, ptrue = cases[0]
@@ -427,7 +432,9 @@ def grad_main(args):
                                "kind": "oracle",
                                "sample": f"one stream's gradient of {K} frames at N={N}, FP64 torch autograd on the "
                                          f"host, {t_cpu:.1f} s"}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def conventional_main(args):
@@ -850,6 +857,17 @@ def main():
                                      "worklist_hip_graph": dict(wl_graph, note="persistent work-list launch per N "
                                                                 "group + M-step, captured once as a HIP graph"),
                                      "tiles": "default per N (the mix autotuner keeps them on this workload)"}
+        # ---- the serving loop (32 streams, N 128/256, Poisson arrivals) and the
+        # batched unrolled-frame gradient, summarised (their own modes: --serve, --grad)
+        if args.workload == "uniform" and not args.no_serve_grad:
+            sv = serve_main(args, only=("trace",), emit=False)
+            tr = sv["trace"]
+            out["serving"] = {"workload": sv["config"]["workload"], "continuous_batching": tr["continuous_batching"],
+                              "plain_one_at_a_time": tr["plain_one_at_a_time"]}
+            gr = grad_main(args, emit=False)
+            out["gradient"] = {"workload": gr["config"]["workload"], "value": round(gr["value"], 1),
+                               "unit": gr["unit"], "ms_per_call": round(gr["ms_per_step"], 3),
+                               "one_stream_at_a_time_frames_per_s": round(gr["one_stream_at_a_time"]["frames_per_s"], 1)}
     out["input_generation_s"] = round(t_gen, 1)
     batch.close()
     print(json.dumps(out), flush=True)
