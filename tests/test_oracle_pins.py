@@ -703,6 +703,42 @@ def test_reference_gradient_against_central_differences():
     assert abs(fd - np.sum(g0 * d)) <= 2e-3 * abs(fd)
 
 
+def test_reference_gradient_against_central_differences_eight_frames():
+    """The same at N = 32 over K = 8 frames (the unroll depth of the
+    differentiation workload): the FP64 autograd gradient against central
+    differences of the NumPy oracle's loss with respect to sigma_w, sigma_r,
+    beta_phi and phi0 along a random tip/tilt-free direction.  The loss over
+    eight frames is strongly curved (wrapped phases, the reflectance floor,
+    the choice of the cubic's root), so a step of 1e-3 is dominated by
+    curvature (up to 20 % off at these parameters); steps of 1e-6 (1e-5 for
+    the prior weights) agree to within 1e-4."""
+    from oracle import grad as G
+    N, K = 32, 8
+    st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=3, stream_id=1))
+    a = ddh.aperture(N)
+    frames = [st.frame(n) for n in range(K)]
+    ptrue = st.phase(K - 1)
+    prm = ddh.Params(sigma_w2=st.sigma_w2)
+    sw, sr, bt = float(np.sqrt(st.sigma_w2)), 0.2, 0.5
+    rng = np.random.default_rng(1)
+    phi0 = ddh.remove_tiptilt(0.3 * rng.standard_normal((N, N)), a)
+    L, g0, gsw, gsr, gbt = G.reference_gradient(phi0, sw, sr, bt, frames, ptrue, a, prm)
+    assert abs(L - G.oracle_loss(phi0, sw, sr, bt, frames, ptrue, a, prm)) <= 1e-12 * L
+    args = [sw, sr, bt]
+    for idx, g, h in ((0, gsw, 1e-6), (1, gsr, 1e-5), (2, gbt, 1e-5)):
+        up, dn = list(args), list(args)
+        up[idx] += h
+        dn[idx] -= h
+        fd = (G.oracle_loss(phi0, *up, frames, ptrue, a, prm) - G.oracle_loss(phi0, *dn, frames, ptrue, a, prm)) / (2 * h)
+        assert abs(fd - g) <= 1e-4 * abs(g), (idx, h, fd, g)
+    d = ddh.remove_tiptilt(rng.standard_normal((N, N)), a)
+    d /= np.sqrt(np.mean(d[a > 0] ** 2))
+    h = 1e-6
+    fd = (G.oracle_loss(phi0 + h * d, sw, sr, bt, frames, ptrue, a, prm)
+          - G.oracle_loss(phi0 - h * d, sw, sr, bt, frames, ptrue, a, prm)) / (2 * h)
+    assert abs(fd - np.sum(g0 * d)) <= 1e-4 * abs(fd)
+
+
 def _mbir_case(N=16):
     st = synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=20.0, speed=0.5, config_id=5, stream_id=0))
     return st, ddh.aperture(N), st.frame(0).astype(np.complex128)
