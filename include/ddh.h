@@ -154,9 +154,11 @@ int ddh_set_state(ddh_stream_t s, const float* r, const float* phi, long long n,
 int ddh_frame_count(ddh_stream_t s, long long* n);
 
 /* Synchronise hip_stream and report whether the last frame submitted on s
- * was rejected (DDH_EDATA) or accepted (DDH_OK), or whether a wait of the
- * work-list step (DDH_BATCH_WORKLIST) gave up on s since the last call
- * (DDH_EDEVICE; reported once). */
+ * was rejected (DDH_EDATA) or accepted (DDH_OK), or whether a bounded wait
+ * between workgroups gave up on s since the last call (DDH_EDEVICE; reported
+ * once): a wait of the work-list step (DDH_BATCH_WORKLIST), or a wait of the
+ * first row pass for the statistics of the frame's other rows.  The frame's
+ * result is then unspecified. */
 int ddh_status(ddh_stream_t s, void* hip_stream);
 
 /* Grid size and parameters of a stream. */
@@ -200,7 +202,7 @@ int ddh_strehl(ddh_stream_t s, const float* phi_true, double* S, void* hip_strea
  * all the group's streams, as (stream, stage, tile) items that workgroups
  * claim in dependency order from one queue per XCD, so that the stages of
  * different streams overlap -- followed by the M-step launch (two launches
- * per iteration instead of five).  Results are bit-identical to the default
+ * per iteration instead of four).  Results are bit-identical to the default
  * launches.  Every wait of an item on the previous stage of its stream is
  * bounded; a wait that gives up lets the launch finish, and ddh_status then
  * reports DDH_EDEVICE for that stream and clears its work-list control
@@ -227,10 +229,11 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * and launch count calls[k] since timing was enabled, and its name to
  * names[k] (static strings).  Kinds: 0 stats, 1 finalize, 2 row-ifft,
  * 3 col-fused, 4 row-fft, 5 m-step, 6 begin (frame start), 7 frame_worklist
- * (the persistent launch of a DDH_BATCH_WORKLIST batch).  The combine of
- * the stats partials runs inside the first row pass of a frame, and an eager
- * step passes the frame start to the stats kernel, so kinds 1 and 6 stay at
- * zero launches in a timed step. */
+ * (the persistent launch of a DDH_BATCH_WORKLIST batch), 8 stats_row_ifft
+ * (the first row pass of a frame with the Normalize/RemoveTipTilt statistics
+ * formed in the same launch; an eager step's first EM iteration starts with
+ * it, later iterations with row-ifft).  The frame start is passed to that
+ * kernel, so kinds 0, 1 and 6 stay at zero launches in a timed eager step. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 

@@ -19,7 +19,6 @@ enum ScalarSlot {
 
 // Stats partials per block: mean_re, mean_im, M2, sum phi, sum (i-c) phi, sum (j-c) phi.
 constexpr int PART_STRIDE = 8;
-constexpr int STATS_PIX_PER_BLOCK = 4096;
 
 // Device-visible descriptor of one stream; an array of these (grouped by N)
 // lives in device memory for every plan.
@@ -30,7 +29,7 @@ struct StreamDesc {
   float2* T;           // row-pass output / (kappa, theta~) after the second row pass
   float2* U;           // column-pass output
   float* bb;           // |b|^2 from the column pass
-  float* part;         // stats partials, PART_STRIDE floats per stats block
+  float* part;         // statistics records, PART_STRIDE floats per grid row
   float* scal;         // SC_COUNT floats
   // the aperture a (D_a), one byte per pixel: prior weight of the aperture
   // neighbours in twelfths (bits 0-3: 2 per edge and 1 per diagonal
@@ -66,6 +65,8 @@ struct StreamDesc {
 constexpr int CTL_TICKETS = 0;    // [0, 16): one ticket counter per XCD queue
 constexpr int CTL_FINISHED = 16;  // workgroups of the launch that have finished
 constexpr int CTL_STAGE = 32;     // [32, 36): completed items per stage (stats, row1, col, row2)
+constexpr int CTL_ROWS = 40;      // fused first row pass: rows whose statistics records are stored
+constexpr int CTL_ROWS_DONE = 41; // fused first row pass: workgroups past their wait
 constexpr int CTL_GIVEUP = 48;    // nonzero: a wait of this stream gave up
 constexpr int CTL_WORDS = 64;
 constexpr int CTL_MAX_QUEUES = 16;
@@ -79,7 +80,7 @@ struct TileConfig {
 };
 
 // Kernel kinds for per-stage timing.
-enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_BEGIN, KK_FRAME, KK_COUNT };
+enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK_BEGIN, KK_FRAME, KK_ROW1S, KK_COUNT };
 
 // Twiddle tables: exp(-2 pi i m / N) for m < N, for N = 64,128,256,512,
 // concatenated at offsets 0, 64, 192, 448 (total 960).
@@ -124,6 +125,15 @@ hipError_t launch_mstep(StreamDesc* const* dptrs, int count, int N, int k, int u
 hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int mode,
                         const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned* ctl0, int nq,
                         int lag, unsigned spin_limit, int giveup, int whole_image, float share, hipStream_t st);
+
+// First EM iteration's first row pass of `count` streams of one N with the
+// frame's Normalize and RemoveTipTilt statistics formed in the same launch
+// (replaces launch_stats + the k = 0 launch_row1; same results).  Frame start
+// as for launch_stats.  spin_limit: polls before a block's wait for its
+// stream's other rows gives up (the stream's give-up word is then set).
+hipError_t launch_row1s(StreamDesc* const* dptrs, int count, int N, const float2* tw, int with_phi,
+                        const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned spin_limit,
+                        const TileConfig& tc, hipStream_t st);
 
 // Plain batched unitary 2D DFT (no fusion): rows into work, columns into out.
 hipError_t launch_fft2(int N, int count, const float2* in, float2* out, float2* work,

@@ -358,6 +358,29 @@ __device__ __forceinline__ XcdBlock xcd_block() {
 }
 
 // ---------------------------------------------------------------------------
+// Cross-workgroup synchronisation helpers (work-list kernel, fused first row
+// pass).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned xcc_id() {
+  // hwreg(HW_REG_XCC_ID, 0, 4): the XCD the wave runs on
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+}
+// Invalidate this CU's vector L1 (lines another CU of the XCD may have
+// rewritten since they were cached here); the L2 is the XCD's coherence point.
+__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
+// lgkmcnt(0): this wave's LDS stores have completed.  Issued after the store
+// of the next ticket, which the loop-top barrier publishes: on that loop's
+// back edge the compiler has been seen to place no LDS wait before the
+// barrier, and another wave could then read the previous ticket.
+__device__ __forceinline__ void lds_stores_done() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+__device__ __forceinline__ unsigned ctl_load(gptr<unsigned> p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ctl_add(gptr<unsigned> p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // Frame start arguments: this frame's y and current state buffer per stream
 // of a launch (at most 64 streams per launch).
 // ---------------------------------------------------------------------------
@@ -379,79 +402,93 @@ __global__ void k_begin(StreamDesc* const* dptrs, FrameArgs a, int count) {
 }
 
 // ---------------------------------------------------------------------------
-// k_stats: per 4096-pixel block, mean and centred power of y (two passes over
-// registers), and the plane-fit sums of phi over the pupil.
-// grid (N*N/4096, streams), block 256
+// Normalize (Eq. 4) and RemoveTipTilt statistics, one record per grid row
+// (PART_STRIDE floats): the sum of y over the row, the power of y about the
+// row's own mean, and the sums of phi and of (j - c) phi over the row's pupil
+// pixels.  The row's T = N/E threads each hold E of its values, at the
+// positions the first row transform loads (first_pos), sum them in a fixed
+// order and then across the T lanes by an xor butterfly (every lane ends with
+// the same bits), so the stats kernel, the work list's stats items and the
+// first row pass form each row's record bit for bit alike.
 // ---------------------------------------------------------------------------
-// Body of one stats block (item) of one stream: y is the stream's frame and
-// cur its current state buffer; writes the block's partial record.
+template <int T>
+__device__ __forceinline__ float row_sum(float x) {
+#pragma unroll
+  for (int off = T / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+// yv, phv, gv: the thread's y, phi and aperture bytes; phi counts on the
+// pupil only, and not at all without the tip/tilt plane (with_phi = 0);
+// t: the thread's lane within the row.
+template <int N>
+__device__ __forceinline__ void row_record(const float2 (&yv)[Plan<N>::E], const float (&phv)[Plan<N>::E],
+                                           const unsigned (&gv)[Plan<N>::E], int with_phi, int t, float (&rec)[5]) {
+  constexpr int E = Plan<N>::E, T = N / E;
+  constexpr float c = 0.5f * (float)(N - 1);
+  float sr = 0.f, si = 0.f;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    sr += yv[i].x;
+    si += yv[i].y;
+  }
+  sr = row_sum<T>(sr);
+  si = row_sum<T>(si);
+  const float mr = sr * (1.0f / (float)N), mi = si * (1.0f / (float)N);
+  float m2 = 0.f, p0 = 0.f, p1 = 0.f;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const float dr = yv[i].x - mr, di = yv[i].y - mi;
+    m2 += dr * dr + di * di;
+    const float pm = (with_phi && geo_in(gv[i])) ? phv[i] : 0.0f;
+    p0 += pm;
+    p1 += ((float)first_pos<N, +1>(i, t) - c) * pm;
+  }
+  rec[0] = sr;
+  rec[1] = si;
+  rec[2] = row_sum<T>(m2);
+  rec[3] = row_sum<T>(p0);
+  rec[4] = row_sum<T>(p1);
+}
+// rows per stats block (256 threads) and stats blocks per stream
+template <int N>
+struct StatsGeom {
+  static constexpr int T = N / Plan<N>::E, RPB = 256 / T, BLOCKS = N / RPB;
+};
+
+// Body of one stats block (item: rows [item RPB, (item + 1) RPB)) of one
+// stream: y is the stream's frame and cur its current state buffer; writes the
+// rows' records.
 template <int N>
 __device__ __forceinline__ void stats_body(const StreamDesc& D, const float2* y, int cur, int item, int with_phi,
-                                           float* red, int tid) {
-  const int base = item * STATS_PIX_PER_BLOCK;
-  constexpr float c = 0.5f * (float)(N - 1);
-  float2 v[16];
-  float ph[16];
-  const float2* yv = glb(y);
-  const float* phi = glb(D.phi[cur]);
+                                           int tid) {
+  constexpr int E = Plan<N>::E, T = N / E;
+  const int line = tid / T, t = tid - line * T;
+  const int row = item * StatsGeom<N>::RPB + line;
+  const auto yr = glb(y) + row * N;
+  const auto phi = glb(D.phi[cur]) + row * N;
   // descriptor fields are read once, here: read inside the loops they would
   // be re-read after every store (which may alias the descriptor) and each
   // re-read waits for every memory operation in flight
-  const auto geo = glb(D.geo);
-  float* out = glb(D.part) + item * PART_STRIDE;
-  // every global read is issued up front: y, and phi on the pupil
+  const auto geo = glb(D.geo) + row * N;
+  const auto out = glb(D.part) + row * PART_STRIDE;
+  // every global read is issued up front; phi is loaded at every pixel
+  // (branch-free: a load under a per-pixel branch makes the compiler wait for
+  // all loads in flight at each join) and masked to the pupil afterwards
+  float2 yv[E];
+  float phv[E];
+  unsigned gv[E];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = yv[base + k * 256 + tid];
-  // phi is loaded at every pixel (branch-free: a load under a per-pixel
-  // branch makes the compiler wait for all loads in flight at each join) and
-  // masked to the pupil afterwards with the aperture bytes
-  if (with_phi) {
-    unsigned gg[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ph[k] = phi[base + k * 256 + tid];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) gg[k] = geo[base + k * 256 + tid];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ph[k] = geo_in(gg[k]) ? ph[k] : 0.0f;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ph[k] = 0.0f;
+  for (int i = 0; i < E; ++i) {
+    const int n = first_pos<N, +1>(i, t);
+    yv[i] = yr[n];
+    phv[i] = phi[n];
+    gv[i] = geo[n];
   }
-  float s[2] = {0.f, 0.f};
+  float rec[5];
+  row_record<N>(yv, phv, gv, with_phi, t, rec);
+  if (t == 0) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    s[0] += v[k].x;
-    s[1] += v[k].y;
-  }
-  block_sum<2>(s, red);
-  const float mr = s[0] * (1.0f / STATS_PIX_PER_BLOCK), mi = s[1] * (1.0f / STATS_PIX_PER_BLOCK);
-  float m2[1] = {0.f};
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const float dr = v[k].x - mr, di = v[k].y - mi;
-    m2[0] += dr * dr + di * di;
-  }
-  block_sum<1>(m2, red);
-  float ps[3] = {0.f, 0.f, 0.f};
-  if (with_phi) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int idx = base + k * 256 + tid;
-      const int i = idx / N, j = idx % N;
-      const float p = ph[k];  // zero off the pupil
-      ps[0] += p;
-      ps[1] += ((float)i - c) * p;
-      ps[2] += ((float)j - c) * p;
-    }
-    block_sum<3>(ps, red);
-  }
-  if (tid == 0) {
-    out[0] = mr;
-    out[1] = mi;
-    out[2] = m2[0];
-    out[3] = ps[0];
-    out[4] = ps[1];
-    out[5] = ps[2];
+    for (int q = 0; q < 5; ++q) out[q] = rec[q];
   }
 }
 
@@ -463,13 +500,12 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
   const XcdBlock xb = xcd_block();
   StreamDesc* const dp = use_args == 2 ? a.d[xb.strm] : dptrs[xb.strm];
   const auto& D = desc_ref(dp);
-  __shared__ float red[6 * 16];
   // frame start: from the arguments (block 0 stores them in the descriptor
   // for the later kernels; no block of this launch reads them there) or from
   // the descriptor
   const float2* y = use_args ? a.y[xb.strm] : D.y;
   const int cur = use_args ? a.cur[xb.strm] : D.cur;
-  stats_body<N>(D, y, cur, xb.item, with_phi, red, threadIdx.x);
+  stats_body<N>(D, y, cur, xb.item, with_phi, threadIdx.x);
   // after the body's descriptor reads (a store that may alias the
   // descriptor would make later reads of it wait for all memory in flight)
   if (use_args && xb.item == 0 && threadIdx.x == 0) {
@@ -481,44 +517,78 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
 }
 
 // ---------------------------------------------------------------------------
-// Combine the stats partials of one stream (fixed order, FP64 combine of at
-// most 64 records by one wavefront) into mean, scale, plane coefficients and
-// the reject flag: out[SC_*].  Called by the first wave of a block.
+// Combine the row records of one stream (fixed order, FP64) into mean, scale,
+// plane coefficients and the reject flag: out[SC_*].  Called by the first
+// wave of a block; lane l takes rows l, l + 64, ...  The centred power is
+// the rows' own centred powers plus N times the spread of the row means.
+// ATOMIC: the records are read with device-coherent loads (they were written
+// by other workgroups of the same launch).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
-// Lane l < nb of a wave loads stats block l's partials.
-template <class Desc>
-__device__ __forceinline__ void load_partials(const Desc& D, float (&p)[6]) {
+template <bool ATOMIC, class Desc>
+__device__ __forceinline__ void combine_stats(const Desc& D, int with_phi, float* out) {
   const int lane = threadIdx.x & 63;
-  const int nb = (D.N * D.N) / STATS_PIX_PER_BLOCK;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) p[q] = 0.f;
-  if (lane < nb) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) p[q] = glb(D.part)[lane * PART_STRIDE + q];
-  }
-}
-template <class Desc>
-__device__ void combine_partials(const Desc& D, int with_phi, const float (&pf)[6], float* out) {
-  const int lane = threadIdx.x & 63;
+  // a 32-thread block (the smallest row tiling) has each thread take lanes l
+  // and l + 32 of the 64-lane tree, so that every tiling sums alike
+  const bool half = blockDim.x < 64;
   const int N = D.N;
-  const int nb = (N * N) / STATS_PIX_PER_BLOCK;
-  double p[6];
+  const int R = N / 64;  // rows per lane (N >= 64)
+  const auto part = glb(D.part);
+  auto rd = [&](int row, int q) -> float {
+    if constexpr (ATOMIC)
+      return __hip_atomic_load(part + row * PART_STRIDE + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      return part[row * PART_STRIDE + q];
+  };
+  // sum over the 64 lanes: first lane l with lane l ^ 32, then a butterfly
+  auto tree = [&](double a0, double a1) {
+    double x = half ? a0 + a1 : a0 + __shfl_xor(a0, 32, 64);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) p[q] = pf[q];
-  const double mr = wave_sum_d(p[0]) / nb, mi = wave_sum_d(p[1]) / nb;
-  const double dr = lane < nb ? p[0] - mr : 0.0, di = lane < nb ? p[1] - mi : 0.0;
-  const double m2 = wave_sum_d(p[2]) + (double)STATS_PIX_PER_BLOCK * wave_sum_d(dr * dr + di * di);
-  const double s0 = wave_sum_d(p[3]), s1 = wave_sum_d(p[4]), s2 = wave_sum_d(p[5]);
+    for (int off = 16; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+  };
+  const double c = 0.5 * (double)(N - 1);
+  double acc[2][6];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[h][q] = 0.0;
+    if (h == 1 && !half) continue;
+    for (int k = 0; k < R; ++k) {
+      const int row = lane + 32 * h + 64 * k;
+      const float v0 = rd(row, 0), v1 = rd(row, 1), v2 = rd(row, 2), v3 = rd(row, 3), v4 = rd(row, 4);
+      acc[h][0] += v0;
+      acc[h][1] += v1;
+      acc[h][2] += v2;
+      acc[h][3] += v3;
+      acc[h][4] += ((double)row - c) * (double)v3;
+      acc[h][5] += v4;
+    }
+  }
+  const double npx = (double)N * (double)N;
+  const double mr = tree(acc[0][0], acc[1][0]) / npx, mi = tree(acc[0][1], acc[1][1]) / npx;
+  // second pass over the row sums (read again rather than held in registers)
+  double dd[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1 && !half) continue;
+    for (int k = 0; k < R; ++k) {
+      const int row = lane + 32 * h + 64 * k;
+      const double er = (double)rd(row, 0) / (double)N - mr, ei = (double)rd(row, 1) / (double)N - mi;
+      dd[h] += er * er + ei * ei;
+    }
+  }
+  const double m2 = tree(acc[0][2], acc[1][2]) + (double)N * tree(dd[0], dd[1]);
+  const double s0 = tree(acc[0][3], acc[1][3]), s1 = tree(acc[0][4], acc[1][4]), s2 = tree(acc[0][5], acc[1][5]);
   if (lane != 0) return;
   const bool ok = (m2 > 0.0) && isfinite(m2) && isfinite(mr) && isfinite(mi);
   out[SC_MU_RE] = (float)mr;
   out[SC_MU_IM] = (float)mi;
-  out[SC_SCALE] = ok ? (float)sqrt((double)N * (double)N / m2) : 0.0f;
+  out[SC_SCALE] = ok ? (float)sqrt(npx / m2) : 0.0f;
   out[SC_FLAG] = ok ? 0.0f : 1.0f;
   double c0 = 0, c1 = 0, c2 = 0;
   if (with_phi) {
@@ -533,17 +603,11 @@ __device__ void combine_partials(const Desc& D, int with_phi, const float (&pf)[
   out[SC_C1] = (float)c1;
   out[SC_C2] = (float)c2;
 }
-template <class Desc>
-__device__ void combine_stats(const Desc& D, int with_phi, float* out) {
-  float p[6];
-  load_partials(D, p);
-  combine_partials(D, with_phi, p, out);
-}
 
 // k_finalize: standalone combine (diagnostic path).  grid (streams), block 64
 __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int with_phi) {
   const auto& D = desc_ref(dptrs[blockIdx.x]);
-  combine_stats(D, with_phi, glb(D.scal));
+  combine_stats<false>(D, with_phi, glb(D.scal));
 }
 
 // ---------------------------------------------------------------------------
@@ -554,10 +618,16 @@ __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int w
 // Body of one row1 block (item = LPW rows) of one stream with frame yf and
 // current state buffer cur.  STAGE_TW: stage the twiddles into s_tw here
 // (otherwise the caller has).  lds holds LPW * RowLds<N>::STRIDE entries.
-template <int N, int LPW, bool STAGE_TW>
+// FUSE: this block also forms its rows' statistics records (the first EM
+// iteration of a frame, fin), publishes them with device-coherent stores,
+// and waits (bounded by spin_limit polls; a wait that gives up sets the
+// stream's give-up word) until all N rows of its stream have been published
+// before the combine; ctl: the stream's control words.
+template <int N, int LPW, bool STAGE_TW, bool FUSE = false>
 __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf, int cur, int item,
                                           const float2* __restrict__ tw, int k, int use_plane, int fin, int with_phi,
-                                          float2* lds, float2* s_tw, float* scs, int tid) {
+                                          float2* lds, float2* s_tw, float* scs, int tid,
+                                          gptr<unsigned> ctl = nullptr, unsigned spin_limit = 0) {
   constexpr int E = Plan<N>::E, T = N / E;
   const int line = tid / T, t = tid - line * T;
   const int row = item * LPW + line;
@@ -580,10 +650,40 @@ __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf,
     for (int i = tid; i < N; i += LPW * T) s_tw[i] = tw[i];
   float sc[SC_COUNT];
   if (fin) {
-    // first EM iteration of a frame: every block combines the stats partials
+    if constexpr (FUSE) {
+      float rec[5];
+      row_record<N>(yv, phv, gv, with_phi, t, rec);
+      if (t == 0) {
+        const auto out = glb(D.part) + row * PART_STRIDE;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) __hip_atomic_store(out + q, rec[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's records are stored
+      __syncthreads();
+      if (tid == 0) {
+        ctl_add(ctl + CTL_ROWS, (unsigned)LPW);
+        unsigned polls = 0;
+        while (ctl_load(ctl + CTL_ROWS) < (unsigned)N) {
+          if (++polls > spin_limit) {
+            __hip_atomic_store(ctl + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+    }
+    // first EM iteration of a frame: every block combines the row records
     // itself (identical arithmetic in all blocks); block 0 publishes them
-    if (tid < 64) combine_stats(D, with_phi, scs);
+    if (tid < 64) combine_stats<FUSE>(D, with_phi, scs);
     __syncthreads();
+    if constexpr (FUSE) {
+      // the last of the stream's blocks past its wait clears the counters
+      if (tid == 0 && ctl_add(ctl + CTL_ROWS_DONE, 1u) + 1 == (unsigned)(N / LPW)) {
+        __hip_atomic_store(ctl + CTL_ROWS, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctl + CTL_ROWS_DONE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     if (item == 0 && tid < SC_COUNT) glb(D.scal)[tid] = scs[tid];
 #pragma unroll
     for (int q = 0; q < SC_COUNT; ++q) sc[q] = scs[q];
@@ -625,6 +725,45 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
   const XcdBlock xb = xcd_block();
   const auto& D = desc_ref(dptrs[xb.strm]);
   row1_body<N, LPW, true>(D, D.y, D.cur, xb.item, tw, k, use_plane, fin, with_phi, lds, s_tw, scs, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// k_row1s: the first row pass of a frame's first EM iteration with the
+// Normalize and RemoveTipTilt statistics formed in the same launch (no
+// separate stats launch).  Each block forms its rows' records, publishes them
+// with device-coherent stores and waits until its stream's N rows are all
+// published, then combines them like k_row1.  Blocks map to (row block,
+// stream) as in the other frame kernels (a stream's blocks consecutive on one
+// XCD), and the dispatcher starts blocks in increasing order, so when a
+// block waits, every earlier block has started and a stream's other blocks
+// are among the next to start once earlier streams' blocks end: no deadlock.
+// Waits are bounded all the same: one that gives up sets the stream's give-up
+// word.  Four waves per SIMD (a few bytes of spill): the row data stay live
+// through the wait, and at three waves per SIMD a 64-stream batch needed a
+// second, partial generation of blocks (37 against 29 us at 64 x N = 256).
+// grid (N/LPW, streams), block LPW * N/E
+// ---------------------------------------------------------------------------
+template <int N, int LPW>
+__global__ __launch_bounds__(LPW*(N / Plan<N>::E)) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_row1s(StreamDesc** dptrs, FrameArgs a, int use_args,
+                                                              const float2* __restrict__ tw, int with_phi,
+                                                              unsigned spin_limit) {
+  __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
+  __shared__ float2 s_tw[N];
+  __shared__ float scs[SC_COUNT];
+  const XcdBlock xb = xcd_block();
+  StreamDesc* const dp = use_args == 2 ? a.d[xb.strm] : dptrs[xb.strm];
+  const auto& D = desc_ref(dp);
+  const float2* y = use_args ? a.y[xb.strm] : D.y;
+  const int cur = use_args ? a.cur[xb.strm] : D.cur;
+  row1_body<N, LPW, true, true>(D, y, cur, xb.item, tw, 0, with_phi, 1, with_phi, lds, s_tw, scs, threadIdx.x,
+                                glb(D.ctl), spin_limit);
+  // after the body's descriptor reads: the frame start for the later kernels
+  if (use_args && xb.item == 0 && threadIdx.x == 0) {
+    const auto d = glb(dp);
+    d->y = y;
+    d->cur = cur;
+    if (use_args == 2) glb(dptrs)[xb.strm] = dp;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -857,24 +996,6 @@ struct FrameTiles {  // rows per row item and columns per column item at 256 thr
   static constexpr int LDS = ROWL > COLL ? ROWL : COLL;
 };
 
-__device__ __forceinline__ unsigned xcc_id() {
-  // hwreg(HW_REG_XCC_ID, 0, 4): the XCD the wave runs on
-  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
-}
-// Invalidate this CU's vector L1 (lines another CU of the XCD may have
-// rewritten since they were cached here); the L2 is the XCD's coherence point.
-__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
-// lgkmcnt(0): this wave's LDS stores have completed.  Issued after the store
-// of the next ticket, which the loop-top barrier publishes: on that loop's
-// back edge the compiler has been seen to place no LDS wait before the
-// barrier, and another wave could then read the previous ticket.
-__device__ __forceinline__ void lds_stores_done() { __builtin_amdgcn_s_waitcnt(0xC07F); }
-__device__ __forceinline__ unsigned ctl_load(gptr<unsigned> p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned ctl_add(gptr<unsigned> p, unsigned v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_frame(StreamDesc** dptrs, int count, FrameArgs a, int use_args,
@@ -884,11 +1005,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   constexpr int LPW = FT::LPW, W = FT::W;
   __shared__ float2 lds[FT::LDS];
   __shared__ float2 s_tw[N];
-  __shared__ float red[6 * 16];
   __shared__ float scs[SC_COUNT];
   __shared__ int s_ticket;
   const int fin = k == 0, first = (mode && k == 0) ? 1 : 0;
-  const int nA = fin ? (N * N) / STATS_PIX_PER_BLOCK : 0, nB = N / LPW, nC = N / W, nD = N / LPW;
+  const int nA = fin ? StatsGeom<N>::BLOCKS : 0, nB = N / LPW, nC = N / W, nD = N / LPW;
   const int s0 = fin ? 0 : 1;  // first stage present
   const int q = (int)(xcc_id() % (unsigned)nq);
   const int Sq = q < count ? (count - q + nq - 1) / nq : 0;
@@ -959,7 +1079,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
     // ---- the item (block bodies of the eager kernels)
     if (stage == 0) {
-      stats_body<N>(D, y, cur, item, mode, red, tid);
+      stats_body<N>(D, y, cur, item, mode, tid);
       if (use_args && item == 0 && threadIdx.x == 0) {
         // the later launches of the frame (M-step, diagnostics) read these
         const auto d = glb(dp);
@@ -1763,7 +1883,7 @@ hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi
       }
     const int mode = ys ? (ds ? 2 : 1) : 0;
 #define DDH_X(NN)                                                                                  \
-  hipLaunchKernelGGL(k_stats<NN>, dim3((NN * NN) / STATS_PIX_PER_BLOCK, n), dim3(256), 0, st, list + off, \
+  hipLaunchKernelGGL(k_stats<NN>, dim3(StatsGeom<NN>::BLOCKS, n), dim3(256), 0, st, list + off, \
                      with_phi, a, mode);                                                            \
   break;
     switch (N) {
@@ -1869,6 +1989,51 @@ hipError_t launch_row1(StreamDesc* const* d, int count, int N, const float2* tw,
 #define DDH_X(NN) return row1_n<NN>(d, count, tw, k, use_plane, fin, with_phi, tc.row_lines, st)
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
+}
+template <int N>
+static hipError_t row1s_n(StreamDesc** list, int n, const FrameArgs& a, int use_args, const float2* tw, int with_phi,
+                          unsigned spin_limit, int lpw, hipStream_t st) {
+  constexpr int T = N / Plan<N>::E;
+#define DDH_R1S(L)                                                                                           \
+  case L:                                                                                                    \
+    hipLaunchKernelGGL((k_row1s<N, L>), dim3(N / L, n), dim3(L * T), 0, st, list, a, use_args, tw, with_phi, \
+                       spin_limit);                                                                          \
+    break;
+  switch (lpw) {
+    DDH_R1S(4) DDH_R1S(8) DDH_R1S(16) DDH_R1S(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef DDH_R1S
+  return hipGetLastError();
+}
+hipError_t launch_row1s(StreamDesc* const* dptrs, int count, int N, const float2* tw, int with_phi,
+                        const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned spin_limit,
+                        const TileConfig& tc, hipStream_t st) {
+  if (!lpw_ok(N, tc.row_lines)) return hipErrorInvalidValue;
+  StreamDesc** list = const_cast<StreamDesc**>(dptrs);
+  for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
+    FrameArgs a{};
+    const int n = count - off < FRAME_ARGS_MAX ? count - off : FRAME_ARGS_MAX;
+    if (ys)
+      for (int i = 0; i < n; ++i) {
+        a.y[i] = ys[off + i];
+        a.cur[i] = curs[off + i];
+        a.d[i] = ds ? ds[off + i] : nullptr;
+      }
+    const int use_args = ys ? (ds ? 2 : 1) : 0;
+    hipError_t e = hipSuccess;
+#define DDH_X(NN) e = row1s_n<NN>(list + off, n, a, use_args, tw, with_phi, spin_limit, tc.row_lines, st)
+    switch (N) {
+      case 64: DDH_X(64); break;
+      case 128: DDH_X(128); break;
+      case 256: DDH_X(256); break;
+      case 512: DDH_X(512); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef DDH_X
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
 }
 hipError_t launch_col(StreamDesc* const* d, int count, int N, const float2* tw, int k, int do_rinit,
                       const TileConfig& tc, hipStream_t st) {

@@ -229,7 +229,7 @@ TileConfig tiles_for(int N) {
 }
 
 const char* kKindNames[KK_COUNT] = {"stats", "finalize", "row_ifft", "col_fused", "row_fft", "m_step", "begin",
-                                    "frame_worklist"};
+                                    "frame_worklist", "stats_row_ifft"};
 
 // XCDs of a device (queues of the work-list kernel), cached per device.
 int xcd_count(int dev) {
@@ -292,10 +292,12 @@ struct Group {
 };
 
 // Work-list (persistent frame kernel) settings of a batch.
+constexpr unsigned kSpinLimit = 1u << 20;  // polls before a cross-workgroup wait gives up
+
 struct Worklist {
   int nq = 1;                   // XCD queues
   int lag = 2;                  // slots between consecutive stages of a stream
-  unsigned spin = 1u << 20;     // polls before a wait gives up
+  unsigned spin = kSpinLimit;   // polls before a wait gives up
   int giveup = 0;               // failure-path test: every wait gives up at once
 };
 
@@ -365,14 +367,15 @@ namespace {
 // The EM iterations of one frame (everything after the stats launch) for
 // `ngroups` groups of streams whose descriptor pointers sit at
 // dptrs[g.off, g.off + g.count).
+// first_row1_done: the k = 0 row pass has run (fused with the statistics).
 template <class OnLaunch>
 int enqueue_iters(StreamDesc** dptrs, const Group* groups, int ngroups, int n_k, int mode, hipStream_t st,
-                  OnLaunch&& around) {
+                  OnLaunch&& around, bool first_row1_done = false) {
   hipError_t e;
   const int iters = mode ? n_k : 1;
   for (int k = 0; k < iters; ++k) {
     const int first = (mode && k == 0) ? 1 : 0;
-    for (int q = 0; q < ngroups; ++q) {
+    for (int q = 0; q < ngroups && !(k == 0 && first_row1_done); ++q) {
       const Group& g = groups[q];
       e = around(KK_ROW1,
                  [&] { return launch_row1(dptrs + g.off, g.count, g.N, g.tw, k, first, k == 0, mode, g.tc, st); });
@@ -402,15 +405,16 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
                   hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr,
                   StreamDesc* const* ds = nullptr) {
   hipError_t e;
+  // the statistics and the first row pass as one launch per group
   for (const Group& g : groups) {
-    e = around(KK_STATS, [&] {
-      return launch_stats(dptrs + g.off, g.count, g.N, mode, ys ? ys + g.off : nullptr, ys ? curs + g.off : nullptr,
-                          ds ? ds + g.off : nullptr, st);
+    e = around(KK_ROW1S, [&] {
+      return launch_row1s(dptrs + g.off, g.count, g.N, g.tw, mode, ys ? ys + g.off : nullptr,
+                          ys ? curs + g.off : nullptr, ds ? ds + g.off : nullptr, kSpinLimit, g.tc, st);
     });
-    if (e != hipSuccess) return hip_fail(e, "launch_stats");
+    if (e != hipSuccess) return hip_fail(e, "launch_row1s");
   }
   (void)total;
-  return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around);
+  return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around, true);
 }
 
 // One frame on the work-list path: per EM iteration one persistent launch
@@ -465,7 +469,7 @@ int set_device_of(int dev) {
 int single_step(ddh_stream_t s, const void* y, hipStream_t st, int mode) {
   const float2* yp = static_cast<const float2*>(y);
   const int iters = mode ? s->prm.n_k : 1;
-  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
+  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw, s->h.ctl}};
   if (mode && s->use_graph) {
     // the replayed graph reads the frame start from the descriptor
     hipError_t e = launch_begin(s->dptr, &yp, &s->parity, 1, st);
@@ -539,7 +543,6 @@ struct StreamLayout {
   size_t r0, r1, p0, p1, T, U, bb, part, scal, ctl, desc, dptr, diag, geo, total;
   explicit StreamLayout(int N) {
     const size_t px = (size_t)N * N;
-    const int nb = (int)(px / STATS_PIX_PER_BLOCK) > 0 ? (int)(px / STATS_PIX_PER_BLOCK) : 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
       size_t o = off;
@@ -553,7 +556,7 @@ struct StreamLayout {
     T = take(px * 8);
     U = take(px * 8);
     bb = take(px * 4);
-    part = take((size_t)nb * PART_STRIDE * 4);
+    part = take((size_t)N * PART_STRIDE * 4);  // one statistics record per grid row
     scal = take(SC_COUNT * 4);
     ctl = take(CTL_WORDS * 4);  // zeroed with the scratch at creation
     desc = take(sizeof(StreamDesc));
@@ -798,7 +801,7 @@ int ddh_mbir(ddh_stream_t s, const void* y, int iters, int reset_every, void* hi
   if (!y || iters < 0 || reset_every < 1) return DDH_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const float2* yp = static_cast<const float2*>(y);
-  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw}};
+  std::vector<Group> g{{s->N, 0, 1, tiles_for(s->N), s->tw, s->h.ctl}};
   for (int it = 0; it < iters; ++it) {
     // a reset is the frame prologue with Eq. (3) and one EM iteration; the
     // other iterations are plain EM
@@ -1300,7 +1303,7 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
     std::vector<Group> groups;
     while (p1 < count && streams[v->order[p1]]->prm.n_k == n_k) {
       const int N = streams[v->order[p1]]->N;
-      Group g{N, p1 - p0, 0, tiles_for(N), streams[v->order[p1]]->tw};
+      Group g{N, p1 - p0, 0, tiles_for(N), streams[v->order[p1]]->tw, streams[v->order[p1]]->h.ctl};
       while (p1 < count && streams[v->order[p1]]->prm.n_k == n_k && streams[v->order[p1]]->N == N) {
         ++g.count;
         ++p1;
