@@ -130,10 +130,11 @@ hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2
 // frame's Normalize and RemoveTipTilt statistics formed in the same launch
 // (replaces launch_stats + the k = 0 launch_row1; same results).  Frame start
 // as for launch_stats.  spin_limit: polls before a block's wait for its
-// stream's other rows gives up (the stream's give-up word is then set).
+// stream's other rows gives up (the stream's give-up word is then set); nq:
+// the device's XCD count.
 hipError_t launch_row1s(StreamDesc* const* dptrs, int count, int N, const float2* tw, int with_phi,
                         const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned spin_limit,
-                        const TileConfig& tc, hipStream_t st);
+                        int nq, const TileConfig& tc, hipStream_t st);
 
 // Plain batched unitary 2D DFT (no fusion): rows into work, columns into out.
 hipError_t launch_fft2(int N, int count, const float2* in, float2* out, float2* work,

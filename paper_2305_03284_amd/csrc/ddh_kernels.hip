@@ -619,15 +619,18 @@ __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int w
 // current state buffer cur.  STAGE_TW: stage the twiddles into s_tw here
 // (otherwise the caller has).  lds holds LPW * RowLds<N>::STRIDE entries.
 // FUSE: this block also forms its rows' statistics records (the first EM
-// iteration of a frame, fin), publishes them with device-coherent stores,
-// and waits (bounded by spin_limit polls; a wait that gives up sets the
-// stream's give-up word) until all N rows of its stream have been published
-// before the combine; ctl: the stream's control words.
+// iteration of a frame, fin), publishes them, and waits (bounded by
+// spin_limit polls; a wait that gives up sets the stream's give-up word)
+// until all N rows of its stream have been published before the combine;
+// ctl: the stream's control words.  local: every block of the stream runs on
+// this XCD, so the records go through its L2 (plain stores, completed before
+// the count; the CU's L1 invalidated after the wait); otherwise they are
+// written and read with device-coherent accesses.
 template <int N, int LPW, bool STAGE_TW, bool FUSE = false>
 __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf, int cur, int item,
                                           const float2* __restrict__ tw, int k, int use_plane, int fin, int with_phi,
                                           float2* lds, float2* s_tw, float* scs, int tid,
-                                          gptr<unsigned> ctl = nullptr, unsigned spin_limit = 0) {
+                                          gptr<unsigned> ctl = nullptr, unsigned spin_limit = 0, bool local = false) {
   constexpr int E = Plan<N>::E, T = N / E;
   const int line = tid / T, t = tid - line * T;
   const int row = item * LPW + line;
@@ -656,7 +659,12 @@ __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf,
       if (t == 0) {
         const auto out = glb(D.part) + row * PART_STRIDE;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) __hip_atomic_store(out + q, rec[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = 0; q < 5; ++q) {
+          if (local)
+            out[q] = rec[q];
+          else
+            __hip_atomic_store(out + q, rec[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's records are stored
       __syncthreads();
@@ -670,12 +678,18 @@ __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf,
           }
           __builtin_amdgcn_s_sleep(2);
         }
+        if (local) l1_invalidate();
       }
       __syncthreads();
     }
     // first EM iteration of a frame: every block combines the row records
     // itself (identical arithmetic in all blocks); block 0 publishes them
-    if (tid < 64) combine_stats<FUSE>(D, with_phi, scs);
+    if (tid < 64) {
+      if (FUSE && !local)
+        combine_stats<true>(D, with_phi, scs);
+      else
+        combine_stats<false>(D, with_phi, scs);
+    }
     __syncthreads();
     if constexpr (FUSE) {
       // the last of the stream's blocks past its wait clears the counters
@@ -746,7 +760,7 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 template <int N, int LPW>
 __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_row1s(StreamDesc** dptrs, FrameArgs a, int use_args,
                                                               const float2* __restrict__ tw, int with_phi,
-                                                              unsigned spin_limit) {
+                                                              unsigned spin_limit, int nq) {
   __shared__ float2 lds[LPW * RowLds<N>::STRIDE];
   __shared__ float2 s_tw[N];
   __shared__ float scs[SC_COUNT];
@@ -755,8 +769,15 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) __attribute__((amdgpu_waves_p
   const auto& D = desc_ref(dp);
   const float2* y = use_args ? a.y[xb.strm] : D.y;
   const int cur = use_args ? a.cur[xb.strm] : D.cur;
+  // xcd_block keeps a stream's blocks on XCD L mod 8 when 8 divides the
+  // streams and the device has 8 XCDs; a block found elsewhere (XCC_ID)
+  // marks its stream's frame as failed
+  const int L = blockIdx.x + blockIdx.y * gridDim.x;
+  const bool local = nq == 8 && gridDim.y % 8 == 0;
+  if (local && threadIdx.x == 0 && (int)xcc_id() != L % 8)
+    __hip_atomic_store(glb(D.ctl) + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   row1_body<N, LPW, true, true>(D, y, cur, xb.item, tw, 0, with_phi, 1, with_phi, lds, s_tw, scs, threadIdx.x,
-                                glb(D.ctl), spin_limit);
+                                glb(D.ctl), spin_limit, local);
   // after the body's descriptor reads: the frame start for the later kernels
   if (use_args && xb.item == 0 && threadIdx.x == 0) {
     const auto d = glb(dp);
@@ -1992,12 +2013,12 @@ hipError_t launch_row1(StreamDesc* const* d, int count, int N, const float2* tw,
 }
 template <int N>
 static hipError_t row1s_n(StreamDesc** list, int n, const FrameArgs& a, int use_args, const float2* tw, int with_phi,
-                          unsigned spin_limit, int lpw, hipStream_t st) {
+                          unsigned spin_limit, int nq, int lpw, hipStream_t st) {
   constexpr int T = N / Plan<N>::E;
 #define DDH_R1S(L)                                                                                           \
   case L:                                                                                                    \
     hipLaunchKernelGGL((k_row1s<N, L>), dim3(N / L, n), dim3(L * T), 0, st, list, a, use_args, tw, with_phi, \
-                       spin_limit);                                                                          \
+                       spin_limit, nq);                                                                      \
     break;
   switch (lpw) {
     DDH_R1S(4) DDH_R1S(8) DDH_R1S(16) DDH_R1S(32)
@@ -2008,7 +2029,7 @@ static hipError_t row1s_n(StreamDesc** list, int n, const FrameArgs& a, int use_
 }
 hipError_t launch_row1s(StreamDesc* const* dptrs, int count, int N, const float2* tw, int with_phi,
                         const float2* const* ys, const int* curs, StreamDesc* const* ds, unsigned spin_limit,
-                        const TileConfig& tc, hipStream_t st) {
+                        int nq, const TileConfig& tc, hipStream_t st) {
   if (!lpw_ok(N, tc.row_lines)) return hipErrorInvalidValue;
   StreamDesc** list = const_cast<StreamDesc**>(dptrs);
   for (int off = 0; off < count; off += FRAME_ARGS_MAX) {
@@ -2022,7 +2043,7 @@ hipError_t launch_row1s(StreamDesc* const* dptrs, int count, int N, const float2
       }
     const int use_args = ys ? (ds ? 2 : 1) : 0;
     hipError_t e = hipSuccess;
-#define DDH_X(NN) e = row1s_n<NN>(list + off, n, a, use_args, tw, with_phi, spin_limit, tc.row_lines, st)
+#define DDH_X(NN) e = row1s_n<NN>(list + off, n, a, use_args, tw, with_phi, spin_limit, nq, tc.row_lines, st)
     switch (N) {
       case 64: DDH_X(64); break;
       case 128: DDH_X(128); break;

@@ -405,11 +405,15 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
                   hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr,
                   StreamDesc* const* ds = nullptr) {
   hipError_t e;
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const int nq = xcd_count(dev);
   // the statistics and the first row pass as one launch per group
   for (const Group& g : groups) {
     e = around(KK_ROW1S, [&] {
       return launch_row1s(dptrs + g.off, g.count, g.N, g.tw, mode, ys ? ys + g.off : nullptr,
-                          ys ? curs + g.off : nullptr, ds ? ds + g.off : nullptr, kSpinLimit, g.tc, st);
+                          ys ? curs + g.off : nullptr, ds ? ds + g.off : nullptr, kSpinLimit, nq, g.tc, st);
     });
     if (e != hipSuccess) return hip_fail(e, "launch_row1s");
   }
