@@ -233,7 +233,13 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * (the first row pass of a frame with the Normalize/RemoveTipTilt statistics
  * formed in the same launch; an eager step's first EM iteration starts with
  * it, later iterations with row-ifft).  The frame start is passed to that
- * kernel, so kinds 0, 1 and 6 stay at zero launches in a timed eager step. */
+ * kernel, so kinds 0, 1 and 6 stay at zero launches in a timed eager step
+ * of a one-lane batch.  A batch with several lanes (and a server call with
+ * several N groups) forms the statistics with a launch of their own (kind 0)
+ * before row-ifft instead, since its lanes' launches run at the same time
+ * and share the device with the fused pass's waiting blocks; the
+ * environment variable DDH_FUSED_STATS (0 or 1, read once per process)
+ * overrides that choice.  Both forms give bit-identical results. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 

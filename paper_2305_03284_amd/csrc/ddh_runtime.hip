@@ -325,6 +325,7 @@ struct ddh_batch_s {
   hipGraphExec_t gexec = nullptr;
   bool capturing = false;             // enqueueing into the graph capture (frame start from descriptors)
   bool worklist = false;              // DDH_BATCH_WORKLIST: persistent frame kernel
+  bool fuse_stats = true;             // statistics formed in the first row pass (k_row1s)
   Worklist wl;
   std::vector<const float2*> yord;
   std::vector<int> curord;       // host parity of each stream, in descriptor order
@@ -361,12 +362,19 @@ struct ddh_server_s {
 
 namespace {
 
-// Enqueue one frame (mode 1: DDH frame with prologue; mode 0: plain EM) for
-// the streams in `dptrs` (grouped by N).  `ev` (optional) records events
-// around every launch.
-// The EM iterations of one frame (everything after the stats launch) for
+// Whether a frame of `lanes` concurrently running lanes forms its statistics
+// in the first row pass: with one lane; DDH_FUSED_STATS=0/1 overrides.
+bool fused_stats_for(int lanes) {
+  static const int env = [] {
+    const char* v = getenv("DDH_FUSED_STATS");
+    return v && (v[0] == '0' || v[0] == '1') ? v[0] - '0' : -1;
+  }();
+  return env >= 0 ? env == 1 : lanes <= 1;
+}
+
+// The EM iterations of one frame (everything after the statistics) for
 // `ngroups` groups of streams whose descriptor pointers sit at
-// dptrs[g.off, g.off + g.count).
+// dptrs[g.off, g.off + g.count); `around` wraps every launch (timing).
 // first_row1_done: the k = 0 row pass has run (fused with the statistics).
 template <class OnLaunch>
 int enqueue_iters(StreamDesc** dptrs, const Group* groups, int ngroups, int n_k, int mode, hipStream_t st,
@@ -400,11 +408,30 @@ int enqueue_iters(StreamDesc** dptrs, const Group* groups, int ngroups, int n_k,
   return DDH_OK;
 }
 
+// Enqueue one frame (mode 1: DDH frame with prologue; mode 0: plain EM) for
+// the streams in `dptrs` (grouped by N).  Frame start from ys/curs/ds
+// (nullptr: from the descriptors).  fuse: the statistics are formed in the
+// first row pass (k_row1s, one launch per group); otherwise by a statistics
+// launch before the k = 0 row pass.  Launches of other lanes that run at the
+// same time share the device with k_row1s's waiting blocks, so batches with
+// several lanes use the separate launch.
 template <class OnLaunch>
 int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int total, int n_k, int mode,
                   hipStream_t st, OnLaunch&& around, const float2* const* ys = nullptr, const int* curs = nullptr,
-                  StreamDesc* const* ds = nullptr) {
+                  StreamDesc* const* ds = nullptr, bool fuse = true) {
   hipError_t e;
+  (void)total;
+  if (!fuse) {
+    // the statistics as a launch of their own, then the k = 0 row pass
+    for (const Group& g : groups) {
+      e = around(KK_STATS, [&] {
+        return launch_stats(dptrs + g.off, g.count, g.N, mode, ys ? ys + g.off : nullptr,
+                            ys ? curs + g.off : nullptr, ds ? ds + g.off : nullptr, st);
+      });
+      if (e != hipSuccess) return hip_fail(e, "launch_stats");
+    }
+    return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around);
+  }
   int dev = 0;
   e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -417,7 +444,6 @@ int enqueue_frame(StreamDesc** dptrs, const std::vector<Group>& groups, int tota
     });
     if (e != hipSuccess) return hip_fail(e, "launch_row1s");
   }
-  (void)total;
   return enqueue_iters(dptrs, groups.data(), (int)groups.size(), n_k, mode, st, around, true);
 }
 
@@ -1024,6 +1050,7 @@ static int batch_create_impl(const ddh_stream_t* streams, int count, int flags,
   b->wl.nq = xcd_count(dev);
   b->wl.giveup = (flags & DDH_BATCH_TEST_GIVEUP) ? 1 : 0;
   if (const char* lag = getenv("DDH_WORKLIST_LAG")) b->wl.lag = std::max(1, std::min(64, atoi(lag)));
+  b->fuse_stats = fused_stats_for(nlanes);
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
   if (e != hipSuccess) {
     delete b;
@@ -1135,7 +1162,7 @@ static int batch_enqueue(ddh_batch_t b, const std::vector<Group>& groups, int co
                          const float2* const* ys, const int* cs) {
   if (b->worklist)
     return enqueue_frame_worklist(b->dptrs, groups.data(), (int)groups.size(), b->n_k, 1, st, around, b->wl, ys, cs);
-  return enqueue_frame(b->dptrs, groups, count, b->n_k, 1, st, around, ys, cs);
+  return enqueue_frame(b->dptrs, groups, count, b->n_k, 1, st, around, ys, cs, nullptr, b->fuse_stats);
 }
 }  // extern "C++"
 
@@ -1316,7 +1343,7 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
     }
     if (groups.size() == 1) {
       int rc = enqueue_frame(v->list + p0, groups, p1 - p0, n_k, 1, st, NoTiming{}, v->ys.data() + p0,
-                             v->curs.data() + p0, v->ds.data() + p0);
+                             v->curs.data() + p0, v->ds.data() + p0, fused_stats_for(1));
       if (rc != DDH_OK) return rc;
     } else {  // the N groups (at most 4) on their own lanes, so that their launches overlap
       DDH_CHECK(hipEventRecord(v->fork, st));
@@ -1324,7 +1351,8 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
         DDH_CHECK(hipStreamWaitEvent(v->lane[l], v->fork, 0));
         const std::vector<Group> one{groups[l]};
         int rc = enqueue_frame(v->list + p0, one, groups[l].count, n_k, 1, v->lane[l], NoTiming{},
-                               v->ys.data() + p0, v->curs.data() + p0, v->ds.data() + p0);
+                               v->ys.data() + p0, v->curs.data() + p0, v->ds.data() + p0,
+                               fused_stats_for((int)groups.size()));
         if (rc != DDH_OK) return rc;
         DDH_CHECK(hipEventRecord(v->join[l], v->lane[l]));
       }
