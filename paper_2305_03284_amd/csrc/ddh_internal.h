@@ -102,7 +102,7 @@ hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const
                         hipStream_t st);
 hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi, const float2* const* ys,
                         const int* curs, StreamDesc* const* ds, hipStream_t st);
-hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st);
+hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st);
 hipError_t launch_row1(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int use_plane,
                        int fin, int with_phi, const TileConfig& tc, hipStream_t st);
 hipError_t launch_col(StreamDesc* const* dptrs, int count, int N, const float2* tw, int k, int do_rinit,

@@ -518,32 +518,48 @@ __global__ __launch_bounds__(256) void k_stats(StreamDesc** dptrs, int with_phi,
 
 // ---------------------------------------------------------------------------
 // Combine the row records of one stream (fixed order, FP64) into mean, scale,
-// plane coefficients and the reject flag: out[SC_*].  Called by the first
-// wave of a block; lane l takes rows l, l + 64, ...  The centred power is
-// the rows' own centred powers plus N times the spread of the row means.
-// ATOMIC: the records are read with device-coherent loads (they were written
-// by other workgroups of the same launch).
+// plane coefficients and the reject flag: out[SC_*].  The block first stages
+// the records in LDS (one round of global loads); the first wave then
+// combines them, lane l taking rows l, l + 64, ...  The centred power is the
+// rows' own centred powers plus N times the spread of the row means.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
-template <bool ATOMIC, class Desc>
-__device__ __forceinline__ void combine_stats(const Desc& D, int with_phi, float* out) {
+// Stage the N row records of a stream into LDS, st[q * N + row] (5 N
+// floats), with the nthr threads of the block.  ATOMIC: the records are read
+// with device-coherent loads (they were written by other workgroups of the
+// same launch).
+template <int N, bool ATOMIC, class Desc>
+__device__ __forceinline__ void stage_records(const Desc& D, float* st, int tid, int nthr) {
+  const auto part = glb(D.part);
+  for (int row = tid; row < N; row += nthr) {
+    const auto rec = part + row * PART_STRIDE;
+    float v[5];
+    if constexpr (ATOMIC) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[q] = __hip_atomic_load(rec + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const float4 a = *reinterpret_cast<gptr<const float4>>(rec);
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2] = a.z;
+      v[3] = a.w;
+      v[4] = rec[4];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) st[q * N + row] = v[q];
+  }
+}
+template <int N, class Desc>
+__device__ __forceinline__ void combine_stats(const Desc& D, int with_phi, const float* st, float* out) {
   const int lane = threadIdx.x & 63;
   // a 32-thread block (the smallest row tiling) has each thread take lanes l
   // and l + 32 of the 64-lane tree, so that every tiling sums alike
   const bool half = blockDim.x < 64;
-  const int N = D.N;
-  const int R = N / 64;  // rows per lane (N >= 64)
-  const auto part = glb(D.part);
-  auto rd = [&](int row, int q) -> float {
-    if constexpr (ATOMIC)
-      return __hip_atomic_load(part + row * PART_STRIDE + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      return part[row * PART_STRIDE + q];
-  };
+  constexpr int R = N / 64;  // rows per lane (N >= 64)
   // sum over the 64 lanes: first lane l with lane l ^ 32, then a butterfly
   auto tree = [&](double a0, double a1) {
     double x = half ? a0 + a1 : a0 + __shfl_xor(a0, 32, 64);
@@ -558,27 +574,29 @@ __device__ __forceinline__ void combine_stats(const Desc& D, int with_phi, float
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[h][q] = 0.0;
     if (h == 1 && !half) continue;
+#pragma unroll 2
     for (int k = 0; k < R; ++k) {
       const int row = lane + 32 * h + 64 * k;
-      const float v0 = rd(row, 0), v1 = rd(row, 1), v2 = rd(row, 2), v3 = rd(row, 3), v4 = rd(row, 4);
-      acc[h][0] += v0;
-      acc[h][1] += v1;
-      acc[h][2] += v2;
+      acc[h][0] += st[row];
+      acc[h][1] += st[N + row];
+      acc[h][2] += st[2 * N + row];
+      const float v3 = st[3 * N + row];
       acc[h][3] += v3;
       acc[h][4] += ((double)row - c) * (double)v3;
-      acc[h][5] += v4;
+      acc[h][5] += st[4 * N + row];
     }
   }
   const double npx = (double)N * (double)N;
   const double mr = tree(acc[0][0], acc[1][0]) / npx, mi = tree(acc[0][1], acc[1][1]) / npx;
-  // second pass over the row sums (read again rather than held in registers)
+  // second pass over the row sums
   double dd[2] = {0.0, 0.0};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (h == 1 && !half) continue;
+#pragma unroll 2
     for (int k = 0; k < R; ++k) {
       const int row = lane + 32 * h + 64 * k;
-      const double er = (double)rd(row, 0) / (double)N - mr, ei = (double)rd(row, 1) / (double)N - mi;
+      const double er = (double)st[row] / (double)N - mr, ei = (double)st[N + row] / (double)N - mi;
       dd[h] += er * er + ei * ei;
     }
   }
@@ -605,9 +623,13 @@ __device__ __forceinline__ void combine_stats(const Desc& D, int with_phi, float
 }
 
 // k_finalize: standalone combine (diagnostic path).  grid (streams), block 64
+template <int N>
 __global__ __launch_bounds__(64) void k_finalize(StreamDesc* const* dptrs, int with_phi) {
+  __shared__ float st[5 * N];
   const auto& D = desc_ref(dptrs[blockIdx.x]);
-  combine_stats<false>(D, with_phi, glb(D.scal));
+  stage_records<N, false>(D, st, threadIdx.x, 64);
+  __syncthreads();
+  combine_stats<N>(D, with_phi, st, glb(D.scal));
 }
 
 // ---------------------------------------------------------------------------
@@ -683,13 +705,17 @@ __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf,
       __syncthreads();
     }
     // first EM iteration of a frame: every block combines the row records
-    // itself (identical arithmetic in all blocks); block 0 publishes them
-    if (tid < 64) {
-      if (FUSE && !local)
-        combine_stats<true>(D, with_phi, scs);
-      else
-        combine_stats<false>(D, with_phi, scs);
-    }
+    // itself (identical arithmetic in all blocks); block 0 publishes them.
+    // The records are staged in the row transform's LDS buffer, which is
+    // free until the transform (5 N floats <= LPW (N + pad) float2).
+    static_assert(5 * N <= 2 * LPW * RowLds<N>::STRIDE, "records do not fit the row buffer");
+    float* const stg = reinterpret_cast<float*>(lds);
+    if (FUSE && !local)
+      stage_records<N, true>(D, stg, tid, LPW * T);
+    else
+      stage_records<N, false>(D, stg, tid, LPW * T);
+    __syncthreads();
+    if (tid < 64) combine_stats<N>(D, with_phi, stg, scs);
     __syncthreads();
     if constexpr (FUSE) {
       // the last of the stream's blocks past its wait clears the counters
@@ -1919,9 +1945,12 @@ hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int with_phi, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(64), 0, st, dptrs, with_phi);
-  return hipGetLastError();
+hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st) {
+#define DDH_X(NN)                                                                     \
+  hipLaunchKernelGGL(k_finalize<NN>, dim3(count), dim3(64), 0, st, dptrs, with_phi); \
+  return hipGetLastError()
+  DDH_DISPATCH_N(N, DDH_X)
+#undef DDH_X
 }
 
 

@@ -907,7 +907,7 @@ int ddh_cost(ddh_stream_t s, const void* y, double* U, void* hip_stream) {
   const float2* yp = static_cast<const float2*>(y);
   hipError_t e = launch_stats(s->dptr, 1, s->N, 0, &yp, &s->parity, nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "stats");
-  e = launch_finalize(s->dptr, 1, 0, st);
+  e = launch_finalize(s->dptr, 1, s->N, 0, st);
   if (e != hipSuccess) return hip_fail(e, "finalize");
   // b into U, work in T (both are scratch between frames)
   e = launch_backproject_cur(s->d, s->N, s->parity, s->tw, s->h.U, s->h.T, st);
