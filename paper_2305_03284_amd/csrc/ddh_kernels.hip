@@ -906,7 +906,8 @@ __device__ __forceinline__ float fatan2(float y, float x) {
 // Per pupil pixel, the phase data term -c cos(phi - theta),
 // c = (2/s2)|yhat||z|, theta = arg(yhat conj z), is majorised at
 // x0 = wrap(phi' - theta) by (kappa/2)(phi - theta~)^2 with kappa = c sinc(x0),
-// theta~ = phi' - x0.  Writes (kappa, theta~) into T (zero off the pupil).
+// theta~ = phi' - x0.  Writes (kappa, theta~) into T on the pupil (T keeps
+// the first row pass's values elsewhere).
 // ---------------------------------------------------------------------------
 // Body of one row2 block (item = LPW rows) of one stream with frame yf and
 // current state buffer cur.
@@ -959,7 +960,8 @@ __device__ __forceinline__ void row2_body(const StreamDesc& D, const float2* yf,
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int m = last_pos<N, -1>(i, t);
-    float2 res = make_float2(0.f, 0.f);
+    // (kappa, theta~) only on the pupil: their readers (the phi update of
+    // the M-step) use them nowhere else
     if (geo_in(gv[i])) {
       const float2 z = cscale(v[i], invN);
       const float2 yh = make_float2((yv[i].x - mu.x) * scale, (yv[i].y - mu.y) * scale);
@@ -974,10 +976,9 @@ __device__ __forceinline__ void row2_body(const StreamDesc& D, const float2* yf,
       const float x0 = fatan2(wi, wr);
       // kappa = c sinc(x0) = (2/s2) |w| sin(x0)/x0 = (2/s2) Im(w)/x0 (x0 = 0: w real, |w| = Re w)
       const float ka = x0 != 0.0f ? c2s * wi * __builtin_amdgcn_rcpf(x0) : c2s * wr;
-      res = make_float2(ka, p - x0);
+      out[m] = make_float2(ka, p - x0);
       if (mat) pmat[m] = p;  // the colour passes update this copy in place
     }
-    out[m] = res;
   }
 }
 
@@ -1454,7 +1455,8 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
         gb[q] = bb4[v];
         gph[q] = pin4[v];
         gw[q] = geo4[v];
-      } else {
+      } else if (BRD) {
+        // off the grid (a vector beyond the region is never staged)
         gr[q] = gb[q] = gph[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         gw[q] = 0u;
       }
@@ -1468,9 +1470,10 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
   // (16-19), pupil-neighbour weight in twelfths (20-23), in-pupil flag (24);
   // -1 when the pixel is off the grid or beyond this pass.  Then |b|^2, kappa
   // and theta~.  The pupil bits come from the stream's per-pixel geometry bytes,
-  // and (kappa, theta~) is read at every own pixel ((0, 0) off the pupil);
-  // the loads are unconditional (a slot without a pixel reads pixel 0) and
-  // the bytes are merged once every load has arrived.
+  // and (kappa, theta~) is read at every own pixel (used only on the pupil;
+  // elsewhere T holds other values); the loads are unconditional (a slot
+  // without a pixel reads pixel 0) and the bytes are merged once every load
+  // has arrived.
   int opk[SLOTS], ogeo[SLOTS];
   float okap[SLOTS], ott[SLOTS], os[SLOTS];
   static_for<0, 4>([&](auto cc) {
@@ -1513,12 +1516,14 @@ __global__ __launch_bounds__((MsGeom<TH, TW>::BT)) __attribute__((amdgpu_waves_p
       const float rv[4] = {gr[q].x, gr[q].y, gr[q].z, gr[q].w};
       const float bv[4] = {gb[q].x, gb[q].y, gb[q].z, gb[q].w};
       const float pv[4] = {gph[q].x, gph[q].y, gph[q].z, gph[q].w};
-      float r[4], p[4] = {0.f, 0.f, 0.f, 0.f};
+      float r[4], p[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         // off the grid r stays 0 (rv = bv = 0; the weight of such a neighbour is 0)
         r[e] = do_rinit ? rinit_of(rv[e], bv[e], lam, alpha, fl) : rv[e];
-        if (geo_in(gw[q] >> (8 * e))) p[e] = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
+        // phi' without a per-pixel branch: formed everywhere, kept on the pupil
+        const float pe = use_plane ? pv[e] - plane_val(c0, c1, c2, gi, gj + e, N) : pv[e];
+        p[e] = geo_in(gw[q] >> (8 * e)) ? pe : 0.f;
       }
       if (border && !(gi >= 0 && gi < N && gj >= 0 && gj < N)) r[0] = r[1] = r[2] = r[3] = 0.f;
       const int o4 = li * RW4 + c4;
