@@ -223,7 +223,10 @@ int ddh_batch_destroy(ddh_batch_t b);
 int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
 
 /* Per-kernel timing of the eager (non-graph) batch step: when enabled, each
- * ddh_batch_step records HIP events around every kernel it launches.
+ * ddh_batch_step launches its kernels one after another on the caller's
+ * stream, each with a pair of HIP events that the launch itself records at
+ * the kernel's start and end (the kernel's execution, as a profiler's kernel
+ * trace sees it, without the dispatch before it).
  * ddh_batch_stage_times synchronises and writes, for each kernel kind k < *n
  * (on input *n is the capacity of the arrays), the summed milliseconds ms[k]
  * and launch count calls[k] since timing was enabled, and its name to

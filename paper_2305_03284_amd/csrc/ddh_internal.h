@@ -87,6 +87,17 @@ enum KernelKind { KK_STATS = 0, KK_FINAL, KK_ROW1, KK_COL, KK_ROW2, KK_MSTEP, KK
 int twiddle_offset(int N);
 constexpr int TWIDDLE_TOTAL = 960;
 
+// Timing of frame-kernel launches: while stop is set, the frame-kernel
+// launches of this thread record start at the first kernel's own start and
+// stop at each kernel's own end (so the last one's end stays), as a profiler
+// would time them; launches counts them.  Set around one launch call by a
+// batch's timing mode and cleared afterwards.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int launches = 0;
+};
+LaunchEvents& launch_events();
+
 // --- launch wrappers (defined in ddh_kernels.hip) ---------------------------
 // dptrs: device array of device descriptor pointers for the streams of one
 // launch (one grid size N for the per-N kernels).  k: EM iteration index

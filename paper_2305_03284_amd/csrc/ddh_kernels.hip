@@ -12,6 +12,7 @@
 // The 2-D DFTs are unitary (scale 1/N per 2-D transform) with the exp(-2 pi i k n/N)
 // kernel for the forward direction.  No MFMA: nothing here is a dense contraction.
 #include "ddh_internal.h"
+#include <hip/hip_ext.h>
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
@@ -1898,6 +1899,25 @@ __global__ void k_copy(float* dst, const float* src, long long n) {
 // ---------------------------------------------------------------------------
 // launch wrappers: runtime dispatch on N and on the tile configuration
 // ---------------------------------------------------------------------------
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+// A frame-kernel launch: through hipExtLaunchKernelGGL when timing events are
+// pending (the kernel itself records the first launch's start and every
+// launch's end), else a plain launch.
+#define DDH_LAUNCH(K, G, B, SH, ST, ...)                                                      \
+  do {                                                                                         \
+    LaunchEvents& le_ = launch_events();                                                       \
+    if (le_.stop) {                                                                            \
+      hipExtLaunchKernelGGL(K, G, B, SH, ST, le_.launches == 0 ? le_.start : nullptr, le_.stop, 0, \
+                            __VA_ARGS__);                                                      \
+      ++le_.launches;                                                                          \
+    } else {                                                                                   \
+      hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                                        \
+    }                                                                                          \
+  } while (0)
+
 #define DDH_DISPATCH_N(N, MACRO) \
   switch (N) {                   \
     case 64: MACRO(64); break;   \
@@ -1916,7 +1936,7 @@ hipError_t launch_begin(StreamDesc* const* dptrs, const float2* const* ys, const
       a.y[i] = ys[off + i];
       a.cur[i] = curs[off + i];
     }
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, dptrs + off, a, n);
+    DDH_LAUNCH(k_begin, dim3(1), dim3(64), 0, st, dptrs + off, a, n);
   }
   return hipGetLastError();
 }
@@ -1935,7 +1955,7 @@ hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi
       }
     const int mode = ys ? (ds ? 2 : 1) : 0;
 #define DDH_X(NN)                                                                                  \
-  hipLaunchKernelGGL(k_stats<NN>, dim3(StatsGeom<NN>::BLOCKS, n), dim3(256), 0, st, list + off, \
+  DDH_LAUNCH(k_stats<NN>, dim3(StatsGeom<NN>::BLOCKS, n), dim3(256), 0, st, list + off, \
                      with_phi, a, mode);                                                            \
   break;
     switch (N) {
@@ -1952,7 +1972,7 @@ hipError_t launch_stats(StreamDesc* const* dptrs, int count, int N, int with_phi
 
 hipError_t launch_finalize(StreamDesc* const* dptrs, int count, int N, int with_phi, hipStream_t st) {
 #define DDH_X(NN)                                                                     \
-  hipLaunchKernelGGL(k_finalize<NN>, dim3(count), dim3(64), 0, st, dptrs, with_phi); \
+  DDH_LAUNCH(k_finalize<NN>, dim3(count), dim3(64), 0, st, dptrs, with_phi); \
   return hipGetLastError()
   DDH_DISPATCH_N(N, DDH_X)
 #undef DDH_X
@@ -1965,7 +1985,7 @@ static hipError_t row1_n(StreamDesc* const* d, int count, const float2* tw, int 
   constexpr int T = N / Plan<N>::E;
 #define DDH_R1(L)                                                                                      \
   case L:                                                                                              \
-    hipLaunchKernelGGL((k_row1<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, fin, \
+    DDH_LAUNCH((k_row1<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, fin, \
                        with_phi);                                                                       \
     break;
   switch (lpw) {
@@ -1981,7 +2001,7 @@ static hipError_t row2_n(StreamDesc* const* d, int count, const float2* tw, int 
   constexpr int T = N / Plan<N>::E;
 #define DDH_R2(L)                                                                                          \
   case L:                                                                                                  \
-    hipLaunchKernelGGL((k_row2<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, mat); \
+    DDH_LAUNCH((k_row2<N, L>), dim3(N / L, count), dim3(L * T), 0, st, d, tw, k, use_plane, mat); \
     break;
   switch (lpw) {
     DDH_R2(4) DDH_R2(8) DDH_R2(16) DDH_R2(32)
@@ -1996,7 +2016,7 @@ static hipError_t col_n(StreamDesc* const* d, int count, const float2* tw, int k
   constexpr int T = N / Plan<N>::E;
 #define DDH_C(W)                                                                                         \
   case W:                                                                                                \
-    hipLaunchKernelGGL((k_col<N, W>), dim3(N / W, count), dim3(W * T), 0, st, d, tw, k, do_rinit, mat); \
+    DDH_LAUNCH((k_col<N, W>), dim3(N / W, count), dim3(W * T), 0, st, d, tw, k, do_rinit, mat); \
     break;
   switch (w) {
     DDH_C(4) DDH_C(8) DDH_C(16) DDH_C(32)
@@ -2010,16 +2030,16 @@ static hipError_t mstep_n(StreamDesc* const* d, int count, int k, int use_plane,
                           hipStream_t st) {
   if (th == 0) {  // four whole-image colour passes
     const dim3 grid((N * N / 4) / 256, count);
-    hipLaunchKernelGGL((k_mpass<N, 0>), grid, dim3(256), 0, st, d, k);
-    hipLaunchKernelGGL((k_mpass<N, 1>), grid, dim3(256), 0, st, d, k);
-    hipLaunchKernelGGL((k_mpass<N, 2>), grid, dim3(256), 0, st, d, k);
-    hipLaunchKernelGGL((k_mpass<N, 3>), grid, dim3(256), 0, st, d, k);
+    DDH_LAUNCH((k_mpass<N, 0>), grid, dim3(256), 0, st, d, k);
+    DDH_LAUNCH((k_mpass<N, 1>), grid, dim3(256), 0, st, d, k);
+    DDH_LAUNCH((k_mpass<N, 2>), grid, dim3(256), 0, st, d, k);
+    DDH_LAUNCH((k_mpass<N, 3>), grid, dim3(256), 0, st, d, k);
     return hipGetLastError();
   }
 #define DDH_M(TH, TW)                                                                                          \
   if (th == TH && tw == TW) {                                                                                  \
     if constexpr (N % TH == 0 && N % TW == 0) {                                                                \
-      hipLaunchKernelGGL((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3((MsGeom<TH, TW>::BT)), 0, st, \
+      DDH_LAUNCH((k_mstep<N, TH, TW>), dim3((N / TH) * (N / TW), count), dim3((MsGeom<TH, TW>::BT)), 0, st, \
                          d, k, use_plane, do_rinit);                                                           \
       return hipGetLastError();                                                                                \
     }                                                                                                          \
@@ -2051,7 +2071,7 @@ static hipError_t row1s_n(StreamDesc** list, int n, const FrameArgs& a, int use_
   constexpr int T = N / Plan<N>::E;
 #define DDH_R1S(L)                                                                                           \
   case L:                                                                                                    \
-    hipLaunchKernelGGL((k_row1s<N, L>), dim3(N / L, n), dim3(L * T), 0, st, list, a, use_args, tw, with_phi, \
+    DDH_LAUNCH((k_row1s<N, L>), dim3(N / L, n), dim3(L * T), 0, st, list, a, use_args, tw, with_phi, \
                        spin_limit, nq);                                                                      \
     break;
   switch (lpw) {
@@ -2138,7 +2158,7 @@ hipError_t launch_frame(StreamDesc* const* dptrs, int count, int N, const float2
     grid = ((grid + nq - 1) / nq) * nq;
     unsigned* c0 = ctl0;
 #define DDH_F(NN)                                                                                           \
-  hipLaunchKernelGGL(k_frame<NN>, dim3(grid), dim3(256), 0, st, list + off, n, a, use_args, tw, k, mode, c0, nq, \
+  DDH_LAUNCH(k_frame<NN>, dim3(grid), dim3(256), 0, st, list + off, n, a, use_args, tw, k, mode, c0, nq, \
                      lag, spin_limit, giveup, whole_image);                                                   \
   break;
     switch (N) {

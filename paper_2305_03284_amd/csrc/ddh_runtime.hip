@@ -1201,11 +1201,18 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream) {
     if (!b->timing) return f();
     hipEvent_t a = pool_event(b), c = pool_event(b);
     if (!a || !c) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, st);
+    // the kernels of f record a at the first one's start and c at the last
+    // one's end (their own execution, without the dispatch in between)
+    LaunchEvents& le = launch_events();
+    le = LaunchEvents{a, c, 0};
+    hipError_t e = f();
+    const int launched = le.launches;
+    le = LaunchEvents{};
     if (e != hipSuccess) return e;
-    e = f();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(c, st);
+    if (launched == 0) {  // nothing launched: an empty interval
+      e = hipEventRecord(a, st);
+      if (e == hipSuccess) e = hipEventRecord(c, st);
+    }
     b->recs.push_back({kind, a, c});
     return e;
   };
