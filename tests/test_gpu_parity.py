@@ -626,6 +626,48 @@ def test_batch_timing_mode_matches_graph():
         np.testing.assert_array_equal(p0, p1)
 
 
+def test_stage_times_are_kernel_durations_within_the_step():
+    """Timing mode: each launch records its own kernel's start and end, so
+    every launched kind has a positive time, and the timed kernels of a step
+    add up to no more than the step's wall time on the device (they run one
+    after another) and to most of it."""
+    import torch
+    D = _ddh()
+    N, S = 256, 16
+    sims = [synth.Stream(synth.StreamSpec(N=N, d_over_r0=8.0, snr=10.0, speed=0.5, config_id=19, stream_id=k))
+            for k in range(S)]
+    pairs = [make_pair(N, sm.sigma_w2) for sm in sims]
+    frames = [[dev(sm.frame(n)) for n in range(2)] for sm in sims]
+    streams = [D.Stream(N, pairs[i][1]) for i in range(S)]
+    b = D.Batch(streams, graph=False)
+    b.set_timing(True)
+    for n in range(2):  # warm-up
+        b.step([frames[i][n % 2] for i in range(S)])
+    b.stage_times()
+    b.set_timing(True)  # clears the sums
+    steps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for n in range(steps):
+        b.step([frames[i][n % 2] for i in range(S)])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = e0.elapsed_time(e1)
+    t = b.stage_times()
+    b.close()
+    for s in streams:
+        s.close()
+    launched = {k: v for k, v in t.items() if v[1]}
+    say("  stage times (ms):", {k: round(v[0], 4) for k, v in launched.items()}, "wall", round(wall, 4))
+    assert {"stats_row_ifft", "col_fused", "row_fft", "m_step"} <= set(launched)
+    assert all(v[1] == steps for v in launched.values())
+    assert all(v[0] > 0.0 for v in launched.values())
+    total = sum(v[0] for v in launched.values())
+    assert total <= wall * 1.02, (total, wall)
+    assert total >= 0.3 * wall, (total, wall)
+
+
 def test_full_size_batch_sampled_against_oracle():
     """64 streams x N=256 batched, as timed by the benchmark; two sampled
     streams are checked against the oracle frame by frame."""
