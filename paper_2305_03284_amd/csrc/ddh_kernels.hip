@@ -1,10 +1,13 @@
 // HIP kernels of the Dynamic DH-MBIR per-frame EM step for gfx950 (MI355X).
 //
 // Per frame and per stream (N x N grid, complex64 data, FP32 arithmetic):
-//   k_stats     y -> block partials of mean / centred power (Eq. (4) Normalize)
-//               phi -> block partials of the least-squares plane (RemoveTipTilt)
-//   k_finalize  partials -> mean, scale, plane coefficients, reject flag
-//   k_row1      rows:    a exp(-j phi') (y - mean) scale, inverse 1-D DFT   (A_phi^H, first half)
+//   k_stats     y -> per-row records of mean / centred power (Eq. (4) Normalize)
+//               phi -> per-row records of the least-squares plane (RemoveTipTilt)
+//   k_finalize  records -> mean, scale, plane coefficients, reject flag
+//   k_row1      rows:    a exp(-j phi') (y - mean) scale, inverse 1-D DFT   (A_phi^H, first half);
+//               at a frame's first EM iteration every block combines the records itself
+//   k_row1s     k_stats and the first k_row1 of a frame as one launch (the blocks of
+//               a stream publish their row records and wait for each other)
 //   k_col       columns: inverse 1-D DFT -> b, Eq. (3) init, E-step -> mu,
 //               forward 1-D DFT of mu                                   (A_phi^H second half, F first half)
 //   k_row2      rows:    forward 1-D DFT -> z = F mu, per-pupil-pixel phase data term (kappa, theta~)
@@ -772,14 +775,15 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) void k_row1(StreamDesc* const
 // k_row1s: the first row pass of a frame's first EM iteration with the
 // Normalize and RemoveTipTilt statistics formed in the same launch (no
 // separate stats launch).  Each block forms its rows' records, publishes them
-// with device-coherent stores and waits until its stream's N rows are all
-// published, then combines them like k_row1.  Blocks map to (row block,
+// (through the XCD's L2 when every block of its stream runs on one XCD,
+// device-coherent otherwise; see row1_body) and waits until its stream's N
+// rows are all published, then combines them like k_row1.  Blocks map to (row block,
 // stream) as in the other frame kernels (a stream's blocks consecutive on one
 // XCD), and the dispatcher starts blocks in increasing order, so when a
 // block waits, every earlier block has started and a stream's other blocks
 // are among the next to start once earlier streams' blocks end: no deadlock.
 // Waits are bounded all the same: one that gives up sets the stream's give-up
-// word.  Four waves per SIMD (a few bytes of spill): the row data stay live
+// word.  Four waves per SIMD (no spill at N <= 256): the row data stay live
 // through the wait, and at three waves per SIMD a 64-stream batch needed a
 // second, partial generation of blocks (37 against 29 us at 64 x N = 256).
 // grid (N/LPW, streams), block LPW * N/E
