@@ -67,6 +67,7 @@ constexpr int CTL_FINISHED = 16;  // workgroups of the launch that have finished
 constexpr int CTL_STAGE = 32;     // [32, 36): completed items per stage (stats, row1, col, row2)
 constexpr int CTL_ROWS = 40;      // fused first row pass: rows whose statistics records are stored
 constexpr int CTL_ROWS_DONE = 41; // fused first row pass: workgroups past their wait
+constexpr int CTL_XCC = 42;       // fused first row pass: XCC_ID + 1 of the stream's first block (0: none yet)
 constexpr int CTL_GIVEUP = 48;    // nonzero: a wait of this stream gave up
 constexpr int CTL_WORDS = 64;
 constexpr int CTL_MAX_QUEUES = 16;

@@ -345,10 +345,12 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red /* >= NV*16
 
 // ---------------------------------------------------------------------------
 // Block -> (item, stream) of a (items, streams) grid.  Workgroups are
-// dispatched round-robin over the 8 XCDs; when the streams split evenly, every
-// block of a stream goes to one XCD (streams [x S/8, (x+1) S/8) on XCD x, the
-// same assignment as the M-step's), so that what one kernel of a stream
-// writes, the next reads through the same L2.
+// dispatched round-robin over the 8 XCDs in linear order; when the streams
+// split evenly, every block of a stream has the same linear index mod 8 and
+// so goes to one XCD (streams [x S/8, (x+1) S/8) share the blocks of index
+// x mod 8, the same grouping as the M-step's), so that what one kernel of a
+// stream writes, the next reads through the same L2 (which XCD that is
+// depends on where the dispatch starts).
 // ---------------------------------------------------------------------------
 struct XcdBlock {
   int item, strm;
@@ -726,6 +728,7 @@ __device__ __forceinline__ void row1_body(const StreamDesc& D, const float2* yf,
       if (tid == 0 && ctl_add(ctl + CTL_ROWS_DONE, 1u) + 1 == (unsigned)(N / LPW)) {
         __hip_atomic_store(ctl + CTL_ROWS, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(ctl + CTL_ROWS_DONE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctl + CTL_XCC, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     if (item == 0 && tid < SC_COUNT) glb(D.scal)[tid] = scs[tid];
@@ -800,13 +803,21 @@ __global__ __launch_bounds__(LPW*(N / Plan<N>::E)) __attribute__((amdgpu_waves_p
   const auto& D = desc_ref(dp);
   const float2* y = use_args ? a.y[xb.strm] : D.y;
   const int cur = use_args ? a.cur[xb.strm] : D.cur;
-  // xcd_block keeps a stream's blocks on XCD L mod 8 when 8 divides the
-  // streams and the device has 8 XCDs; a block found elsewhere (XCC_ID)
-  // marks its stream's frame as failed
-  const int L = blockIdx.x + blockIdx.y * gridDim.x;
+  // Workgroups go to the 8 XCDs round-robin in linear order (from whichever
+  // XCD the dispatch starts at), so xcd_block's grouping by linear index mod
+  // 8 puts every block of a stream on one XCD when 8 divides the streams and
+  // the device has 8 XCDs.  The protocol relies on that, so each block checks
+  // it: the first block of the stream to arrive records its XCC_ID, and a
+  // block on another XCD marks the stream's frame as failed.
   const bool local = nq == 8 && gridDim.y % 8 == 0;
-  if (local && threadIdx.x == 0 && (int)xcc_id() != L % 8)
-    __hip_atomic_store(glb(D.ctl) + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (local && threadIdx.x == 0) {
+    const unsigned me = xcc_id() + 1u;  // 0: not yet recorded
+    unsigned seen = 0u;
+    if (!__hip_atomic_compare_exchange_strong(glb(D.ctl) + CTL_XCC, &seen, me, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) &&
+        seen != me)
+      __hip_atomic_store(glb(D.ctl) + CTL_GIVEUP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   row1_body<N, LPW, true, true>(D, y, cur, xb.item, tw, 0, with_phi, 1, with_phi, lds, s_tw, scs, threadIdx.x,
                                 glb(D.ctl), spin_limit, local);
   // after the body's descriptor reads: the frame start for the later kernels
