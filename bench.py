@@ -601,6 +601,9 @@ def main():
     iters = S * args.steps  # N_k = 1: one EM iteration per stream per step
     value = iters / dt
     ms_per_step = 1e3 * dt / args.steps
+    # after the timed region: every stream's status for its last frame (a
+    # rejected frame or a device-side wait that gave up would show here)
+    statuses = [s.status() for s in streams]
 
     out = {
         "metric": "EM iters/s (batched DDH-MBIR EM step)",
@@ -620,6 +623,7 @@ def main():
                    "launch": ("graph" if args.graph else "eager") + (", work list" if args.worklist else ""),
                    "lanes": "one per N" if args.lanes == 0 else args.lanes,
                    "tiles": {str(k): v for k, v in tiles.items()}},
+        "streams_ok": sum(1 for v in statuses if v == 0) == S,
         "device_warmup": {"ms": args.device_warmup_ms, "steps": n_dw,
                           "note": "untimed batched steps before the warm-up steps (GPU clock ramp)"},
     }
