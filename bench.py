@@ -131,19 +131,23 @@ def mstep_ops(fill):
 
 
 def recorded_traffic(kernel_kind, tiles):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    record (profiles/m_step_traffic.json), or None when the kernel source or
-    the tiling has changed since the counters were taken."""
+    """(HBM bytes per launch of the dominant kernel, note) from the committed
+    counter record (profiles/m_step_traffic.json); the bytes are None when
+    there is no record for the kernel or the kernel source or the tiling has
+    changed since the counters were taken, and the note says which."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "m_step_traffic.json")
     src = os.path.join(ROOT, "paper_2305_03284_amd", "csrc", "ddh_kernels.hip")
     if kernel_kind != "m_step" or not os.path.exists(rec_path):
-        return None
+        return None, "no counter record for this kernel"
     rec = json.load(open(rec_path))
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha256_prefix") != sha or list(rec.get("tiles", [])) != list(tiles):
-        return None
-    return int(rec["traffic_bytes"])
+    if rec.get("source_sha256_prefix") != sha:
+        return None, "kernel source changed since the counters were taken"
+    if list(rec.get("tiles", [])) != list(tiles):
+        return None, "tiling differs from the one the counters were taken with"
+    return int(rec["traffic_bytes"]), ("profiles/m_step_traffic.json: FETCH_SIZE x %.1f + WRITE_SIZE x %.1f per "
+                                       "launch, kernel source %s" % (rec["fetch_scale"], rec["write_scale"], sha))
 
 
 def oracle_params(sigma_w2):
@@ -670,14 +674,16 @@ def main():
         if dom == "m_step" and "Gop_s" in kernels[dom]:
             # the M-step is bound by vector-ALU issue (its HBM traffic takes a
             # fraction of its duration)
+            traffic, tnote = recorded_traffic(dom, tiles.get(args.N, ()))
             out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["Gop_s"],
                                "peak": round(ALU_PEAK_GOPS, 1), "unit": "Gop/s",
                                "frac": round(kernels[dom]["Gop_s"] / ALU_PEAK_GOPS, 4),
-                               "traffic": recorded_traffic(dom, tiles.get(args.N, ()))}
+                               "traffic": traffic, "traffic_note": tnote}
         elif "GB_s" in kernels[dom]:
+            traffic, tnote = recorded_traffic(dom, tiles.get(args.N, ()))
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"], "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
-                               "traffic": recorded_traffic(dom, tiles.get(args.N, ()))}
+                               "traffic": traffic, "traffic_note": tnote}
         step_bytes_floor = 56 * px_total  # compulsory + one global round trip per 2-D FFT
         step_bytes_alg = sum(kb[k] for k in kernels if k in kb) * px_total  # the kernels the step launched
         out["kernels"] = kernels

@@ -601,14 +601,14 @@ def test_batch_of_more_streams_than_one_launch_takes():
             s.close()
 
 
-def test_fused_statistics_pass_identical_over_many_frames():
+@pytest.mark.parametrize("N,S,F", [(64, 64, 24), (256, 64, 3), (512, 16, 3)])
+def test_fused_statistics_pass_identical_over_many_frames(N, S, F):
     """The fused statistics + first row pass synchronises the blocks of each
-    stream through device memory (XCD-local with 64 streams, device-coherent
-    for a single stream): 64 streams of N = 64 over 24 frames in one batch
-    (eager and HIP graph) equal every stream stepped alone, bit for bit, and
-    no stream reports a wait that gave up."""
+    stream through device memory (XCD-local when the streams are a multiple
+    of 8, device-coherent for a single stream): S streams over F frames in one
+    batch (eager and HIP graph) equal every stream stepped alone, bit for bit,
+    and no stream reports a wait that gave up."""
     D = _ddh()
-    N, S, F = 64, 64, 24
     sims = [synth.Stream(synth.StreamSpec(N=N, d_over_r0=6.0, snr=8.0, speed=0.5, config_id=21, stream_id=k))
             for k in range(S)]
     pairs = [make_pair(N, sm.sigma_w2) for sm in sims]
