@@ -632,19 +632,24 @@ def main():
                           "note": "untimed batched steps before the warm-up steps (GPU clock ramp)"},
     }
 
-    # calibration copy for the HBM byte counters: a plain 64 MiB copy of a
-    # source pushed out of the caches by 512 MiB of later writes
-    src = torch.empty(64 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-    flush = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(2.0)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    out["calibration_copy_bytes"] = 64 * 2 ** 20
-    del src, dst, flush
+    def calibration_copy():
+        # for the HBM byte counters: a plain 64 MiB copy of a source pushed out
+        # of the caches by 512 MiB of later writes (after the per-kernel timing,
+        # whose steps would otherwise start with the caches flushed)
+        src = torch.empty(64 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        flush = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 64 * 2 ** 20
+        del src, dst, flush
 
-    if not args.no_extras:
-        # ---- per-kernel timing (eager step, HIP events around every launch on its stream)
+    if args.no_extras:
+        calibration_copy()
+    else:
+        # ---- per-kernel timing (eager step; each launch records its kernel's
+        # start and end with a pair of HIP events)
         batch.set_timing(True)
         for _ in range(args.timing_steps):
             batch.step_ptrs(ptrs[step % args.frames])
@@ -652,6 +657,7 @@ def main():
         st_times = batch.stage_times()
         batch.set_timing(False)
         torch.cuda.synchronize()
+        calibration_copy()
         fill = float(synth.aperture(args.N).sum()) / args.N ** 2 if args.workload == "uniform" else 0.785
         kb = kernel_bytes(args.N, fill)
         kernels = {}
