@@ -242,7 +242,10 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * before row-ifft instead, since its lanes' launches run at the same time
  * and share the device with the fused pass's waiting blocks; the
  * environment variable DDH_FUSED_STATS (0 or 1, read once per process)
- * overrides that choice.  Both forms give bit-identical results. */
+ * overrides that choice.  Both forms give bit-identical results.  The fused
+ * pass takes 32 rows per block for groups of 8 or more streams at N >= 256
+ * and the row passes' row_lines otherwise (DDH_FUSED_LINES = 4, 8, 16 or 32,
+ * read once per process, overrides); results do not depend on it. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 
