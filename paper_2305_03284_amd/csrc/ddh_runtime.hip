@@ -379,13 +379,16 @@ int fused_lines(int N, int count, int row_lines) {
 }
 
 // Whether a frame of `lanes` concurrently running lanes forms its statistics
-// in the first row pass: with one lane; DDH_FUSED_STATS=0/1 overrides.
-bool fused_stats_for(int lanes) {
+// in the first row pass: with one lane, or when the frame is replayed as a
+// HIP graph (measured on the 2:5:1 mixed-size batch: eager launches 376k
+// EM iters/s with the separate statistics launch against 370k fused, graph
+// replay 383k-385k against 388k fused); DDH_FUSED_STATS=0/1 overrides.
+bool fused_stats_for(int lanes, bool graph) {
   static const int env = [] {
     const char* v = getenv("DDH_FUSED_STATS");
     return v && (v[0] == '0' || v[0] == '1') ? v[0] - '0' : -1;
   }();
-  return env >= 0 ? env == 1 : lanes <= 1;
+  return env >= 0 ? env == 1 : (lanes <= 1 || graph);
 }
 
 // The EM iterations of one frame (everything after the statistics) for
@@ -1068,7 +1071,7 @@ static int batch_create_impl(const ddh_stream_t* streams, int count, int flags,
   b->wl.nq = xcd_count(dev);
   b->wl.giveup = (flags & DDH_BATCH_TEST_GIVEUP) ? 1 : 0;
   if (const char* lag = getenv("DDH_WORKLIST_LAG")) b->wl.lag = std::max(1, std::min(64, atoi(lag)));
-  b->fuse_stats = fused_stats_for(nlanes);
+  b->fuse_stats = fused_stats_for(nlanes, (flags & DDH_BATCH_GRAPH) != 0);
   hipError_t e = hipMalloc(&b->dptrs, sizeof(StreamDesc*) * count);
   if (e != hipSuccess) {
     delete b;
@@ -1368,7 +1371,7 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
     }
     if (groups.size() == 1) {
       int rc = enqueue_frame(v->list + p0, groups, p1 - p0, n_k, 1, st, NoTiming{}, v->ys.data() + p0,
-                             v->curs.data() + p0, v->ds.data() + p0, fused_stats_for(1));
+                             v->curs.data() + p0, v->ds.data() + p0, fused_stats_for(1, false));
       if (rc != DDH_OK) return rc;
     } else {  // the N groups (at most 4) on their own lanes, so that their launches overlap
       DDH_CHECK(hipEventRecord(v->fork, st));
@@ -1377,7 +1380,7 @@ int ddh_server_step(ddh_server_t v, const ddh_stream_t* streams, const void* con
         const std::vector<Group> one{groups[l]};
         int rc = enqueue_frame(v->list + p0, one, groups[l].count, n_k, 1, v->lane[l], NoTiming{},
                                v->ys.data() + p0, v->curs.data() + p0, v->ds.data() + p0,
-                               fused_stats_for((int)groups.size()));
+                               fused_stats_for((int)groups.size(), false));
         if (rc != DDH_OK) return rc;
         DDH_CHECK(hipEventRecord(v->join[l], v->lane[l]));
       }
