@@ -704,6 +704,37 @@ def test_stage_times_are_kernel_durations_within_the_step():
     assert total >= 0.3 * wall, (total, wall)
 
 
+def test_statistics_form_follows_the_lane_rule():
+    """Timing mode shows which form of the frame statistics a batch uses:
+    one lane forms them in the first row pass (stats_row_ifft); several
+    lanes launched eagerly use a statistics launch before the first row
+    pass (stats, row_ifft).  Both give the same states."""
+    D = _ddh()
+    specs = _mixed_specs()[:4]
+    sims = [synth.Stream(sp) for sp in specs]
+    pairs = [make_pair(sp.N, sm.sigma_w2) for sp, sm in zip(specs, sims)]
+    frames = [[dev(sm.frame(n)) for n in range(2)] for sm in sims]
+    res, kinds = [], []
+    for lanes in (1, 0):
+        streams = [D.Stream(sp.N, pairs[i][1]) for i, sp in enumerate(specs)]
+        b = D.Batch(streams, graph=False, lanes=lanes)
+        b.set_timing(True)
+        for n in range(2):
+            b.step([frames[i][n] for i in range(len(specs))])
+        t = b.stage_times()
+        kinds.append({k for k, v in t.items() if v[1]})
+        res.append([state(s) for s in streams])
+        b.close()
+        for s in streams:
+            s.close()
+    say("  launched kinds:", kinds)
+    assert "stats_row_ifft" in kinds[0] and "stats" not in kinds[0]
+    assert "stats" in kinds[1] and "stats_row_ifft" not in kinds[1]
+    for (r0, p0), (r1, p1) in zip(*res):
+        np.testing.assert_array_equal(r0, r1)
+        np.testing.assert_array_equal(p0, p1)
+
+
 def test_full_size_batch_sampled_against_oracle():
     """64 streams x N=256 batched, as timed by the benchmark; two sampled
     streams are checked against the oracle frame by frame."""
