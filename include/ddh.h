@@ -237,16 +237,17 @@ int ddh_batch_step(ddh_batch_t b, const void* const* y, void* hip_stream);
  * formed in the same launch; an eager step's first EM iteration starts with
  * it, later iterations with row-ifft).  The frame start is passed to that
  * kernel, so kinds 0, 1 and 6 stay at zero launches in a timed eager step
- * of a one-lane batch.  A batch with several lanes that is not replayed as
- * a HIP graph (and a server call with several N groups) forms the statistics
- * with a launch of their own (kind 0) before row-ifft instead, since its
- * lanes' launches run at the same time and share the device with the fused
- * pass's waiting blocks (measured faster that way for eager launches, slower
- * for graph replay); the environment variable DDH_FUSED_STATS (0 or 1, read
- * once per process) overrides that choice.  Both forms give bit-identical results.  The fused
- * pass takes 32 rows per block for groups of 8 or more streams at N >= 256
- * and the row passes' row_lines otherwise (DDH_FUSED_LINES = 4, 8, 16 or 32,
- * read once per process, overrides); results do not depend on it. */
+ * of a one-lane batch.  A batch with several lanes created without
+ * DDH_BATCH_GRAPH (and a server call with several N groups) forms the
+ * statistics with a launch of their own (kind 0) before row-ifft instead,
+ * since its lanes' launches run at the same time and share the device with
+ * the fused pass's waiting blocks (measured faster that way for eager
+ * launches, slower for graph replay); the environment variable
+ * DDH_FUSED_STATS (0 or 1, read once per process) overrides that choice.
+ * Both forms give bit-identical results.  The fused pass takes 32 rows per
+ * block for groups of 8 or more streams at N >= 256 and the row passes'
+ * row_lines otherwise (DDH_FUSED_LINES = 4, 8, 16 or 32, read once per
+ * process, overrides); results do not depend on it. */
 int ddh_batch_set_timing(ddh_batch_t b, int enable);
 int ddh_batch_stage_times(ddh_batch_t b, double* ms, long long* calls, const char** names, int* n);
 
